@@ -1,0 +1,247 @@
+#!/usr/bin/env python3
+"""Throughput of the phase-space lattice update on one MI355X.
+
+A step is one lattice time step of the whole lattice: the flow check
+(Eq. 3 CFL on the device), the fused streaming + drift + diffusion pass,
+with the FP64 conservation moments taken once at the end of the timed
+region.  Default workload: 2D periodic 512^2 sites x 33^2 velocities, FP32
+state, Koren limiter, St = 1 (tau_p = 2 pi), kappa = 1e-4, Vmax = 3 u_rms,
+flow from a random streamfunction with k^-3 energy spectrum over
+1 <= |k| <= 32 evolving as OU (tau_f = 1), one fresh flow slice per step,
+all inputs resident in HBM before timing starts.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("phase-space cell updates/s (GCUPS) + % HBM peak; coarse+MLP vs "
+          "fine at equal moment error")
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: (dim, n, nv, vstride, dtype, St, kappa, vmax)
+    "2d-512x512-v33": dict(dim=2, n=512, nv=33, s=1, dtype="f32", St=1.0,
+                           kappa=1e-4, vmax=3.0),
+    "2d-256x256-v65": dict(dim=2, n=256, nv=65, s=1, dtype="f32", St=5.0,
+                           kappa=1e-4, vmax=3.0),
+    "2d-256x256-v17s4": dict(dim=2, n=256, nv=17, s=4, dtype="f32", St=2.0,
+                             kappa=1e-4, vmax=3.0),
+    "1d-16384-v129": dict(dim=1, n=16384, nv=129, s=1, dtype="f32", St=1.0,
+                          kappa=1e-4, vmax=2.0),
+    "1d-256-v33-f64": dict(dim=1, n=256, nv=33, s=1, dtype="f64", St=1.0,
+                           kappa=1e-3, vmax=5.0),
+}
+KERNEL_SOURCES = ["paper_1508_02899_amd/csrc/step2d.h",
+                  "paper_1508_02899_amd/csrc/step1d.hip",
+                  "paper_1508_02899_amd/csrc/device_common.h"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def geometry(w):
+    L = 2 * math.pi
+    h = (w["nv"] - 1) // 2
+    dx = L / w["n"]
+    dv = w["vmax"] / h
+    dt = w["s"] * dx / dv
+    tau_p = w["St"] * L  # tau_flow = L / u_rms = 2 pi
+    return L, dx, dv, dt, tau_p
+
+
+def make_flow(w, nslices, dt, dtype):
+    from paper_1508_02899_amd import inputs
+    L = 2 * math.pi
+    if w["dim"] == 2:
+        return inputs.flow2d_streamfunction(
+            w["n"], L, nslices, kmax=min(32, w["n"] // 4), tau_f=1.0, dt=dt,
+            seed=inputs.seed_for(3), dtype=dtype)
+    return inputs.flow1d(w["n"], L, nslices, modes=32, spectrum="k-5/3",
+                         tau_f=1.0, dt=dt, seed=inputs.seed_for(2),
+                         dtype=dtype)
+
+
+def cpu_baseline(w, name, dx, dv, dt, tau_p):
+    """The FP64 oracle, untouched, on a bounded sample of the workload."""
+    import numpy as np
+
+    import oracle
+    from paper_1508_02899_amd import inputs
+    L = 2 * math.pi
+    if w["dim"] == 2:
+        m = min(w["n"], 256 if w["nv"] <= 33 else 128)
+        steps = 2
+        u = make_flow(w, 1, dt, np.float32)[:, :, :m, :m]
+        f0 = inputs.gaussian_ic(2, m, w["nv"], dx, dv, ny=m)
+        sample = (f"{m}x{m} sites (a crop of the {w['n']}x{w['n']} lattice) "
+                  f"x {w['nv']}^2 velocities, {steps} steps, same parameters")
+        cells = m * m * w["nv"] ** 2
+    else:
+        m = w["n"]
+        steps = 20 if w["nv"] > 33 else 200
+        u = make_flow(w, 1, dt, np.float32)
+        f0 = inputs.gaussian_ic(1, m, w["nv"], dx, dv)
+        sample = f"full {m} x {w['nv']} lattice, {steps} steps"
+        cells = m * w["nv"]
+    t0 = time.perf_counter()
+    oracle.step(f0.astype(np.float64), u.astype(np.float64), dim=w["dim"],
+                dx=dx, tau_p=tau_p, kappa=w["kappa"], dt=dt, nsteps=steps,
+                s=w["s"])
+    el = time.perf_counter() - t0
+    return {"value": cells * steps / el / 1e9, "unit": "GCUPS", "cores": 1,
+            "kind": "oracle", "sample": sample, "seconds": round(el, 3)}
+
+
+def load_traffic(name):
+    path = os.path.join(ROOT, "profiles", f"traffic_{name}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel_hash") != kernel_hash():
+        return None  # counters were taken on another version of the kernel
+    return t.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="2d-512x512-v33",
+                    choices=sorted(WORKLOADS))
+    ap.add_argument("--scheme", default="koren", choices=["koren", "upwind"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the lattice update runs on a single "
+              "MI355X in this build (multi-GPU sharding is not built); use "
+              "--gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1508_02899_amd import Lattice, LatticeSpec, inputs
+
+    w = WORKLOADS[args.workload]
+    L, dx, dv, dt, tau_p = geometry(w)
+    npdt = np.float64 if w["dtype"] == "f64" else np.float32
+    n, nv, dim = w["n"], w["nv"], w["dim"]
+    ny = n if dim == 2 else 1
+    sites = n * ny
+    cells = sites * nv ** dim
+    elem = 8 if w["dtype"] == "f64" else 4
+    K, W = args.steps, args.warmup
+    log(f"bench: workload {args.workload}, {cells} cells, steps {K}, "
+        f"warmup {W}")
+
+    torch.cuda.set_device(0)
+    u_np = make_flow(w, W + K, dt, npdt)
+    f0 = inputs.gaussian_ic(dim, n, nv, dx, dv, ny=ny, dtype=npdt)
+    spec = LatticeSpec(dim=dim, nx=n, ny=ny, nv=nv, dx=dx, vstride=w["s"],
+                       scheme=args.scheme, dtype=w["dtype"], u_hold=1)
+    lat = Lattice(spec)
+    f = torch.from_numpy(f0).cuda()
+    u = torch.from_numpy(u_np).cuda()
+    del u_np
+    cfl, dnum = lat.stability(u, tau_p, w["kappa"], dt)
+    log(f"bench: CFL {cfl:.3f}, kappa dt/dv^2 {dnum:.2e}")
+    m0 = lat.moments(f, dt)
+
+    if W:
+        lat.step(f, u[:W], tau_p, w["kappa"], dt, W)
+        lat.sync()
+    torch.cuda.synchronize()
+    lat.profile(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    lat.step(f, u[W:W + K], tau_p, w["kappa"], dt, K)
+    m1 = lat.moments(f, dt)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = ev0.elapsed_time(ev1)
+    kern_ms, launches = lat.profile_read()
+    lat.profile(False)
+    lat.close()
+    log(f"bench: wall {wall * 1e3:.2f} ms, events {ev_ms:.2f} ms, kernel "
+        f"{kern_ms:.2f} ms over {launches} launches")
+
+    sec = ev_ms / 1e3
+    value = cells * K / sec / 1e9
+    avg_launch_s = kern_ms / 1e3 / max(launches, 1)
+    algo_bytes = 2 * cells * elem + dim * sites * elem  # read f, write f, u
+    achieved = algo_bytes / avg_launch_s / 1e9
+    mass_drift = abs(m1["mass"] - m0["mass"]) / m0["mass"]
+    traffic = load_traffic(args.workload)
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "GCUPS",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(ev_ms / K, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": w["dtype"],
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{args.workload}: {dim}D periodic, {n}^{dim} sites x "
+                         f"{nv}^{dim} velocities (stride {w['s']}), "
+                         f"{w['dtype'].upper()} state, {args.scheme}, "
+                         f"St={w['St']}, kappa={w['kappa']}, "
+                         f"Vmax={w['vmax']} u_rms, synthetic OU flow, "
+                         "one flow slice per step"),
+            "cells": cells,
+            "scheme": args.scheme,
+            "cfl": round(cfl, 4),
+            "mass_drift_rel": mass_drift,
+            "hbm_frac_wall": round(2 * cells * elem * K / sec / 1e9
+                                   / HBM_PEAK_GBS, 4),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "kernel": "k_step2d" if dim == 2 else "k_step1d",
+            "avg_launch_us": round(avg_launch_s * 1e6, 3),
+            "algorithmic_bytes_per_launch": algo_bytes,
+        },
+    }
+    if not args.no_cpu_baseline:
+        log("bench: timing the oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(w, args.workload, dx, dv, dt, tau_p)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,208 @@
+/*
+ * lattice.h -- C ABI of the MI355X phase-space lattice library.
+ *
+ * The library advances the position/velocity phase-space density f(x, v, t)
+ * of diffusive heavy inertial particles with the lattice method of
+ * F. Laenen, G. Krstulovic, J. Bec, "A lattice model for the Eulerian
+ * description of heavy particle suspensions" (arXiv:1508.02899):
+ *
+ *   - phase space is cut into (2d)-dimensional cells on which f is piecewise
+ *     constant (Sec. 2);
+ *   - velocities sit on a lattice v_j = (j - h) dv, j = 0..nv-1,
+ *     h = (nv-1)/2, with dv = vstride * dx / dt, so that the mass of velocity
+ *     index j moves by exactly vstride*(j-h) cells per step (Sec. 2: dx = dv
+ *     dt, vstride = 1);  Vmax = h dv, i.e. dv = 2 Vmax / (nv - 1) (Sec. 3.2,
+ *     Fig. 14 caption);
+ *   - one time step is exact streaming, then the Stokes drift
+ *     (u(x,t) - v)/tau_p of Eq. 5 as finite-volume fluxes across velocity
+ *     faces (first-order upwind or Koren-limited), then velocity diffusion
+ *     kappa d_v^2 f as finite-difference face fluxes (Sec. 2, Eqs. 3-5), with
+ *     zero flux through the outer faces of the velocity domain.
+ *
+ * Everything runs in HIP kernels for gfx950 on the stream bound to the
+ * handle.  State is FP32 (or FP64); the conservation moments are reduced in
+ * FP64 on the GPU.
+ *
+ * Conventions for every function:
+ *   - return 0 on success, a negative LATTICE_E* code on failure; nothing
+ *     throws across the ABI;
+ *   - "device" pointers are HIP device allocations (e.g. torch tensors on
+ *     cuda:0), "host" pointers are ordinary memory;
+ *   - a handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef LATTICE_H
+#define LATTICE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lattice lattice_t;
+
+/* state / flow element type */
+enum { LATTICE_F32 = 0, LATTICE_F64 = 1 };
+
+/* drift scheme (Sec. 2): first-order upwind, or the Koren flux limiter
+ * psi(theta) = max(0, min(1, 1/3 + theta/6, theta)) (Hundsdorfer et al.
+ * 1995) applied to the upwind-split drift fluxes. */
+enum { LATTICE_UPWIND = 0, LATTICE_KOREN = 1 };
+
+/* error codes */
+enum {
+  LATTICE_OK = 0,
+  LATTICE_EINVAL = -1,     /* bad argument (see each function) */
+  LATTICE_ECFL = -2,       /* drift CFL of Eq. 3 violated (see lattice_step) */
+  LATTICE_EDIFF = -3,      /* kappa dt_s / dv^2 >= 1/2 (Eq. 4) */
+  LATTICE_EHIP = -4,       /* HIP runtime error; lattice_last_error explains */
+  LATTICE_ENOMEM = -5,     /* device allocation failed */
+  LATTICE_ENONFINITE = -6, /* moments are NaN or Inf */
+  LATTICE_ENOTSUP = -7     /* valid but not compiled in (2D nv, see below) */
+};
+
+/*
+ * Lattice description.  Layouts (all contiguous, x fastest):
+ *   f : [nv^dim][ny][nx]   velocity plane jv = jy*nv + jx in 2D (jv = j in
+ *                          1D, ny = 1); dtype elements;
+ *   u : [slices][dim][ny][nx]  fluid velocity components, dtype elements.
+ * Limits: nx*ny*nv^dim*sizeof(dtype) < 2^40 and
+ * nv^(dim-1)*nx*ny*sizeof(dtype) < 2^31 (one row of velocity planes).
+ * Compiled velocity lattices: 1D any odd nv in [3, 129] (FP32) or [3, 65]
+ * (FP64); 2D odd nv in [3, 21], 25, 33, 65 (FP32) and 3, 5, 9, 17, 33
+ * (FP64).  Other odd nv >= 3 give LATTICE_ENOTSUP.
+ */
+typedef struct {
+  int32_t dim;     /* 1 or 2 */
+  int64_t nx, ny;  /* spatial sites per direction; ny is ignored (1) in 1D */
+  int32_t nv;      /* velocities per component: odd, >= 3 (paper: 2^n + 1) */
+  int32_t vstride; /* cells moved per velocity index per step; 1 = paper */
+  double dx;       /* spatial spacing (> 0) */
+  int32_t scheme;  /* LATTICE_UPWIND or LATTICE_KOREN */
+  int32_t dtype;   /* LATTICE_F32 or LATTICE_F64 */
+  int32_t nsub;    /* drift+diffusion sub-steps per streaming step (>= 1);
+                      1 = the paper's scheme */
+  int64_t u_hold;  /* steps per u slice within one lattice_step call;
+                      0 = a single slice for the whole call */
+  void* stream;    /* hipStream_t to run on; NULL = the default stream */
+} lattice_desc;
+
+/* Moments of f (Sec. 3.2 mass normalisation and its velocity moments):
+ * with w = dx^d dv^d,  mass = w sum f,  momentum[k] = w sum f v_k,
+ * second_moment[k] = w sum f v_k^2,
+ * variance = sum_k second_moment[k]/mass - |momentum/mass|^2.
+ * Components k >= dim are 0.  nonfinite = 1 if any sum is NaN/Inf. */
+typedef struct {
+  double mass;
+  double momentum[2];
+  double second_moment[2];
+  double variance;
+  int32_t nonfinite;
+} lattice_moments_t;
+
+/* Fill *d with defaults: dim 1, nx 1, ny 1, nv 33, vstride 1, dx 1, Koren,
+ * FP32, nsub 1, u_hold 0, default stream.  EINVAL if d is NULL. */
+int lattice_desc_default(lattice_desc* d);
+
+/* Velocity geometry for a time step dt: *dv = vstride dx / dt,
+ * *vmax = h dv.  Host-only; EINVAL on a bad descriptor or dt <= 0. */
+int lattice_velocity(const lattice_desc* d, double dt, double* dv,
+                     double* vmax);
+
+/*
+ * Validate *d and create a handle that owns a device scratch buffer of the
+ * state's size (the ping-pong twin of f) plus small reduction buffers.
+ * EINVAL: dim not 1/2, nx/ny < 1, nv even or < 3, vstride < 1, dx <= 0,
+ * scheme/dtype unknown, nsub < 1, u_hold < 0, out NULL, sizes past the
+ * limits; ENOTSUP: 2D nv without a compiled kernel; ENOMEM; EHIP.
+ */
+int lattice_init(const lattice_desc* d, lattice_t** out);
+
+/*
+ * Advance f (device, in/out, layout above) by nsteps time steps of length
+ * dt.  Step s of the call applies: exact pull streaming (Sec. 2), then nsub
+ * times [drift (Eq. 5 force at cell centres, upwind or Koren fluxes), then
+ * diffusion (finite-difference fluxes)] with dt_s = dt/nsub; in 2D each of
+ * drift and diffusion is split by velocity axis (vx then vy).  The flow is
+ * sampled at the destination site of the streaming from slice
+ * s / u_hold of u (slice 0 if u_hold == 0).
+ *
+ * u (device, read-only) holds n_u_slices slices; the call needs
+ * ceil(nsteps/u_hold) of them (1 if u_hold == 0), else EINVAL.  tau_p may be
+ * +INFINITY (no drag: drift exactly zero); kappa may be 0 (no diffusion).
+ *
+ * Checked on the host, returned immediately: EINVAL (NULL f/u, misaligned
+ * pointers, dt <= 0 or NaN, tau_p <= 0 or NaN, kappa < 0 or NaN,
+ * nsteps < 0), EDIFF (kappa dt_s/dv^2 >= 1/2, Eq. 4), ECFL when Vmax alone
+ * already violates the drift bound.  Checked on the device: the drift CFL
+ * of Eq. 3, (dt_s/dv) (max|u_k| + Vmax)/tau_p, must be < 1 (upwind) or
+ * <= 1/2 (Koren, the positivity bound of the limited scheme), and u must be
+ * finite; a violation sets a sticky flag that turns every later step into a
+ * no-op (f keeps the state before the call) until the next lattice_sync or
+ * lattice_moments reports LATTICE_ECFL and clears it.
+ *
+ * Asynchronous: kernels are queued on the handle's stream and the call
+ * returns without waiting.  f and u must stay valid until the stream has
+ * passed the call.  The result always ends in f (the library ping-pongs
+ * with its scratch buffer and copies once when nsteps is odd).
+ */
+int lattice_step(lattice_t* L, void* f, const void* u, int64_t n_u_slices,
+                 double tau_p, double kappa, double dt, int64_t nsteps);
+
+/*
+ * FP64 moments of f (device, read-only) for time step dt (which fixes dv),
+ * reduced on the GPU in a fixed order (deterministic) into *out (host).
+ * Synchronous: waits for the stream.  Returns ECFL if the sticky CFL flag
+ * was set by an earlier lattice_step (and clears it), ENONFINITE if a sum
+ * is not finite (out is filled in both cases), EINVAL, EHIP.
+ */
+int lattice_moments(lattice_t* L, const void* f, double dt,
+                    lattice_moments_t* out);
+
+/*
+ * Spatial density rho(x) = dv^dim sum_j f(x, v_j) (the velocity integral
+ * of f, Sec. 3.2) into rho (device, [ny][nx] FP64).  Asynchronous.
+ * EINVAL on NULL pointers or dt <= 0.
+ */
+int lattice_density(lattice_t* L, const void* f, double dt, double* rho);
+
+/*
+ * Largest drift CFL number of Eq. 3 and the diffusion number of Eq. 4 for
+ * the given u slices (device) and parameters: out[0] = (dt_s/dv)
+ * (max|u_k| + Vmax)/tau_p, out[1] = kappa dt_s/dv^2 (out host, 2 doubles).
+ * The max|u| reduction runs on the GPU.  Synchronous.  EINVAL, EHIP.
+ */
+int lattice_stability(lattice_t* L, const void* u, int64_t n_u_slices,
+                      double tau_p, double kappa, double dt, double* out);
+
+/* Copy a state-sized array (device to device) with the library's copy
+ * kernel on the handle's stream.  Asynchronous.  EINVAL on NULL. */
+int lattice_copy_state(lattice_t* L, void* dst, const void* src);
+
+/* Wait for the stream; report LATTICE_ECFL (and clear the flag) if a CFL
+ * violation was flagged since the last report, or EHIP. */
+int lattice_sync(lattice_t* L);
+
+/* Per-launch timing of the streaming/collision kernels with HIP events on
+ * the handle's stream.  enable != 0 starts recording (and resets the
+ * totals); lattice_profile_read waits for the stream and returns the summed
+ * kernel time in milliseconds and the number of timed launches. */
+int lattice_profile(lattice_t* L, int enable);
+int lattice_profile_read(lattice_t* L, double* total_ms, int64_t* launches);
+
+/* Release the handle and its device buffers (waits for the stream).
+ * NULL is accepted. */
+int lattice_destroy(lattice_t* L);
+
+/* Static description of an error code. */
+const char* lattice_strerror(int code);
+
+/* Last detailed error message of the handle (e.g. the HIP error string),
+ * or "" ; valid until the next call on the handle. */
+const char* lattice_last_error(const lattice_t* L);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LATTICE_H */

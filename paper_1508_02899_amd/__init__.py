@@ -1,0 +1,9 @@
+"""MI355X-native phase-space lattice method for diffusive heavy particles.
+
+Implements the lattice update of Laenen, Krstulovic & Bec,
+arXiv:1508.02899 (Sec. 2) as hand-written HIP kernels for gfx950 behind the
+C ABI in ``include/lattice.h``; ``lattice`` is the Python binding and
+``inputs`` the seeded synthetic flows and initial conditions.
+"""
+from .lattice import (Lattice, LatticeError, LatticeLibraryMissing,  # noqa: F401
+                      LatticeSpec, load_library, strerror, velocity)

@@ -1,0 +1,430 @@
+// lattice_host.hip -- C ABI of the phase-space lattice library: argument
+// validation, velocity geometry, stability checks, buffer ownership and the
+// launch sequence of one lattice_step call.  All arithmetic on the state
+// happens in the kernels (step1d.hip, step2d*.hip, aux_kernels.hip).
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "../../include/lattice.h"
+#include "lattice_internal.h"
+
+struct lattice {
+  lattice_desc d;
+  int64_t sites;    // nx * ny
+  int64_t nplanes;  // nv^dim
+  int64_t cells;    // sites * nplanes
+  size_t elem;      // sizeof state element
+  hipStream_t stream;
+  void* scratch = nullptr;      // state-sized ping-pong twin
+  int* flag = nullptr;          // sticky CFL / finiteness flag (device)
+  double* plane_sums = nullptr; // nplanes doubles
+  double* red = nullptr;        // 8 doubles: moments / absmax
+  double* host_red = nullptr;   // pinned mirror of red
+  char msg[512];
+  // profiling
+  bool prof = false;
+  std::vector<hipEvent_t> ev;   // pairs (start, stop)
+  size_t ev_used = 0;
+  double prof_ms = 0.0;
+  int64_t prof_launches = 0;
+};
+
+namespace {
+
+int set_err(lattice_t* L, int code, const char* fmt, ...) {
+  if (L) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(L->msg, sizeof(L->msg), fmt, ap);
+    va_end(ap);
+  }
+  return code;
+}
+
+int hip_err(lattice_t* L, hipError_t e, const char* where) {
+  return set_err(L, LATTICE_EHIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define HIPCHK(L, expr)                            \
+  do {                                             \
+    hipError_t e_ = (expr);                        \
+    if (e_ != hipSuccess) return hip_err(L, e_, #expr); \
+  } while (0)
+
+bool bad_desc(const lattice_desc* d) {
+  if (!d) return true;
+  if (d->dim != 1 && d->dim != 2) return true;
+  if (d->nx < 1 || (d->dim == 2 && d->ny < 1)) return true;
+  if (d->nv < 3 || (d->nv % 2) == 0) return true;
+  if (d->vstride < 1) return true;
+  if (!(d->dx > 0.0) || !isfinite(d->dx)) return true;
+  if (d->scheme != LATTICE_UPWIND && d->scheme != LATTICE_KOREN) return true;
+  if (d->dtype != LATTICE_F32 && d->dtype != LATTICE_F64) return true;
+  if (d->nsub < 1 || d->u_hold < 0) return true;
+  const double elem = d->dtype == LATTICE_F64 ? 8.0 : 4.0;
+  const double ny = d->dim == 2 ? (double)d->ny : 1.0;
+  const double sites = (double)d->nx * ny;
+  const double row = sites * (d->dim == 2 ? (double)d->nv : 1.0) * elem;
+  const double total = sites * pow((double)d->nv, d->dim) * elem;
+  if (row >= 2147483648.0 || total >= 1099511627776.0) return true;
+  if (d->nx >= 2147483647 || ny >= 2147483647) return true;
+  return false;
+}
+
+// Drift bound of Eq. 3 for the scheme: strict CFL < 1 for upwind; CFL <= 1/2
+// for the Koren-limited fluxes (outflow of a cell is at most twice its
+// upwind value, so 2*CFL <= 1 keeps every cell non-negative).
+double cfl_bound(int scheme) { return scheme == LATTICE_KOREN ? 0.5 : 1.0; }
+
+hipError_t record_pair(lattice_t* L, bool stop) {
+  if (!L->prof) return hipSuccess;
+  if (!stop) {
+    if (L->ev_used + 2 > L->ev.size()) {
+      for (int k = 0; k < 64; ++k) {
+        hipEvent_t e;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+        L->ev.push_back(e);
+      }
+    }
+    return hipEventRecord(L->ev[L->ev_used], L->stream);
+  }
+  hipError_t r = hipEventRecord(L->ev[L->ev_used + 1], L->stream);
+  L->ev_used += 2;
+  return r;
+}
+
+// Fold recorded event pairs into the totals (stream must be idle).
+hipError_t prof_drain(lattice_t* L) {
+  for (size_t k = 0; k + 1 < L->ev_used; k += 2) {
+    float ms = 0.f;
+    hipError_t r = hipEventElapsedTime(&ms, L->ev[k], L->ev[k + 1]);
+    if (r != hipSuccess) return r;
+    L->prof_ms += ms;
+    L->prof_launches += 1;
+  }
+  L->ev_used = 0;
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lattice_desc_default(lattice_desc* d) {
+  if (!d) return LATTICE_EINVAL;
+  memset(d, 0, sizeof(*d));
+  d->dim = 1;
+  d->nx = 1;
+  d->ny = 1;
+  d->nv = 33;
+  d->vstride = 1;
+  d->dx = 1.0;
+  d->scheme = LATTICE_KOREN;
+  d->dtype = LATTICE_F32;
+  d->nsub = 1;
+  d->u_hold = 0;
+  d->stream = nullptr;
+  return LATTICE_OK;
+}
+
+int lattice_velocity(const lattice_desc* d, double dt, double* dv,
+                     double* vmax) {
+  if (bad_desc(d) || !(dt > 0.0) || !isfinite(dt) || !dv || !vmax)
+    return LATTICE_EINVAL;
+  *dv = (double)d->vstride * d->dx / dt;
+  *vmax = (double)((d->nv - 1) / 2) * (*dv);
+  return LATTICE_OK;
+}
+
+int lattice_init(const lattice_desc* d, lattice_t** out) {
+  if (!out) return LATTICE_EINVAL;
+  *out = nullptr;
+  if (bad_desc(d)) return LATTICE_EINVAL;
+  if (d->dim == 1 && !lat::step1d_supported(d->nv, d->dtype == LATTICE_F64))
+    return LATTICE_ENOTSUP;
+  if (d->dim == 2 && !lat::step2d_supported(d->nv, d->dtype == LATTICE_F64))
+    return LATTICE_ENOTSUP;
+  lattice_t* L = new (std::nothrow) lattice;
+  if (!L) return LATTICE_ENOMEM;
+  L->d = *d;
+  if (L->d.dim == 1) L->d.ny = 1;
+  L->msg[0] = 0;
+  L->sites = L->d.nx * L->d.ny;
+  L->nplanes = L->d.dim == 1 ? L->d.nv : (int64_t)L->d.nv * L->d.nv;
+  L->cells = L->sites * L->nplanes;
+  L->elem = L->d.dtype == LATTICE_F64 ? 8 : 4;
+  L->stream = (hipStream_t)L->d.stream;
+  hipError_t e = hipMalloc(&L->scratch, (size_t)L->cells * L->elem);
+  if (e != hipSuccess) {
+    delete L;
+    return e == hipErrorOutOfMemory ? LATTICE_ENOMEM : LATTICE_EHIP;
+  }
+  if (hipMalloc(&L->flag, sizeof(int)) != hipSuccess ||
+      hipMalloc(&L->plane_sums, sizeof(double) * (size_t)L->nplanes) !=
+          hipSuccess ||
+      hipMalloc(&L->red, sizeof(double) * 8) != hipSuccess ||
+      hipHostMalloc((void**)&L->host_red, sizeof(double) * 8,
+                    hipHostMallocDefault) != hipSuccess) {
+    lattice_destroy(L);
+    return LATTICE_ENOMEM;
+  }
+  if (lat::launch_clear_flag(L->flag, L->stream) != hipSuccess ||
+      hipStreamSynchronize(L->stream) != hipSuccess) {
+    lattice_destroy(L);
+    return LATTICE_EHIP;
+  }
+  *out = L;
+  return LATTICE_OK;
+}
+
+int lattice_step(lattice_t* L, void* f, const void* u, int64_t n_u_slices,
+                 double tau_p, double kappa, double dt, int64_t nsteps) {
+  if (!L) return LATTICE_EINVAL;
+  L->msg[0] = 0;
+  const lattice_desc& d = L->d;
+  if (!f || !u) return set_err(L, LATTICE_EINVAL, "f or u is NULL");
+  if (((uintptr_t)f % L->elem) || ((uintptr_t)u % L->elem))
+    return set_err(L, LATTICE_EINVAL, "misaligned f or u");
+  if (!(dt > 0.0) || !isfinite(dt))
+    return set_err(L, LATTICE_EINVAL, "dt must be > 0");
+  if (!(tau_p > 0.0)) return set_err(L, LATTICE_EINVAL, "tau_p must be > 0");
+  if (!(kappa >= 0.0) || !isfinite(kappa))
+    return set_err(L, LATTICE_EINVAL, "kappa must be >= 0");
+  if (nsteps < 0) return set_err(L, LATTICE_EINVAL, "nsteps < 0");
+  const int64_t need =
+      d.u_hold > 0 ? (nsteps + d.u_hold - 1) / d.u_hold : 1;
+  if (n_u_slices < need || n_u_slices < 1)
+    return set_err(L, LATTICE_EINVAL, "u holds %lld slices, call needs %lld",
+                   (long long)n_u_slices, (long long)need);
+  if (nsteps == 0) return LATTICE_OK;
+
+  const double dv = (double)d.vstride * d.dx / dt;
+  const int h = (d.nv - 1) / 2;
+  const double vmax = h * dv;
+  const double dts = dt / d.nsub;
+  const double Dn = kappa * dts / (dv * dv);
+  if (!(Dn < 0.5))
+    return set_err(L, LATTICE_EDIFF, "kappa dt_s/dv^2 = %g >= 1/2", Dn);
+  const bool drag = isfinite(tau_p);
+  const double bound = cfl_bound(d.scheme);
+  double umax_ok = 0.0;
+  if (drag) {
+    // (dt_s/dv)(|u| + Vmax)/tau_p within bound  <=>  |u| within umax_ok
+    umax_ok = bound * tau_p * dv / dts - vmax;
+    const double cfl0 = (dts / dv) * vmax / tau_p;
+    if (umax_ok < 0.0 || (d.scheme == LATTICE_UPWIND && !(cfl0 < 1.0)))
+      return set_err(L, LATTICE_ECFL, "Vmax alone gives CFL %g", cfl0);
+  }
+
+  const int64_t slice_len = (int64_t)d.dim * L->sites;
+  const int64_t used = drag ? need : 0;
+  if (used > 0)
+    HIPCHK(L, lat::launch_cfl_check(u, used * slice_len, umax_ok,
+                                    d.scheme == LATTICE_UPWIND ? 1 : 0,
+                                    d.dtype == LATTICE_F64, L->flag,
+                                    L->stream));
+
+  // passes: per step, 1D does everything in one pass (nsub inline); 2D does
+  // one streaming pass plus (nsub - 1) collision-only passes.
+  const int64_t passes_per_step = d.dim == 1 ? 1 : d.nsub;
+  const int64_t passes = nsteps * passes_per_step;
+  void* bufs[2];
+  if (passes % 2 == 0) {
+    bufs[0] = f;
+    bufs[1] = L->scratch;
+  } else {
+    HIPCHK(L, lat::launch_copy(L->scratch, f, L->cells * (int64_t)L->elem,
+                               L->stream));
+    bufs[0] = L->scratch;
+    bufs[1] = f;
+  }
+
+  lat::StepArgs a;
+  a.flag = L->flag;
+  a.nx = d.nx;
+  a.ny = d.ny;
+  a.nv = d.nv;
+  a.alpha_scale = drag ? dts / (dv * tau_p) : 0.0;
+  a.beta = drag ? dts / tau_p : 0.0;
+  a.D = Dn;
+  a.koren = d.scheme == LATTICE_KOREN;
+  a.f64 = d.dtype == LATTICE_F64;
+  int64_t k = 0;
+  for (int64_t s = 0; s < nsteps; ++s) {
+    const int64_t sl = d.u_hold > 0 ? s / d.u_hold : 0;
+    a.u = (const char*)u + (size_t)(sl * slice_len) * L->elem;
+    for (int64_t ps = 0; ps < passes_per_step; ++ps, ++k) {
+      a.fin = bufs[k & 1];
+      a.fout = bufs[(k + 1) & 1];
+      a.shift = ps == 0 ? d.vstride : 0;
+      a.nsub_inline = d.dim == 1 ? d.nsub : 1;
+      HIPCHK(L, record_pair(L, false));
+      hipError_t e = d.dim == 1 ? lat::launch_step1d(a, L->stream)
+                                : lat::launch_step2d(a, L->stream);
+      if (e != hipSuccess) return hip_err(L, e, "step kernel launch");
+      HIPCHK(L, record_pair(L, true));
+    }
+  }
+  return LATTICE_OK;
+}
+
+static int read_flag(lattice_t* L) {
+  int h = 0;
+  hipError_t e = hipMemcpyAsync(&h, L->flag, sizeof(int),
+                                hipMemcpyDeviceToHost, L->stream);
+  if (e != hipSuccess) return hip_err(L, e, "flag copy");
+  e = hipStreamSynchronize(L->stream);
+  if (e != hipSuccess) return hip_err(L, e, "stream sync");
+  if (h) {
+    e = lat::launch_clear_flag(L->flag, L->stream);
+    if (e != hipSuccess) return hip_err(L, e, "flag clear");
+    e = hipStreamSynchronize(L->stream);
+    if (e != hipSuccess) return hip_err(L, e, "stream sync");
+    return set_err(L, LATTICE_ECFL,
+                   "drift CFL bound (Eq. 3) violated or non-finite u");
+  }
+  return LATTICE_OK;
+}
+
+int lattice_moments(lattice_t* L, const void* f, double dt,
+                    lattice_moments_t* out) {
+  if (!L) return LATTICE_EINVAL;
+  L->msg[0] = 0;
+  if (!f || !out || !(dt > 0.0) || !isfinite(dt))
+    return set_err(L, LATTICE_EINVAL, "bad moments arguments");
+  const lattice_desc& d = L->d;
+  const double dv = (double)d.vstride * d.dx / dt;
+  const double w = d.dim == 1 ? d.dx * dv : d.dx * d.dx * dv * dv;
+  HIPCHK(L, lat::launch_moments(f, L->sites, d.nv, d.dim,
+                                d.dtype == LATTICE_F64, w, dv, L->plane_sums,
+                                L->red, L->stream));
+  HIPCHK(L, hipMemcpyAsync(L->host_red, L->red, sizeof(double) * 6,
+                           hipMemcpyDeviceToHost, L->stream));
+  HIPCHK(L, hipStreamSynchronize(L->stream));
+  const double* r = L->host_red;
+  memset(out, 0, sizeof(*out));
+  out->mass = r[0];
+  out->momentum[0] = r[1];
+  out->second_moment[0] = r[3];
+  if (d.dim == 2) {
+    out->momentum[1] = r[2];
+    out->second_moment[1] = r[4];
+  }
+  out->variance = r[5];
+  int nonfinite = 0;
+  for (int i = 0; i < 6; ++i) nonfinite |= !isfinite(r[i]);
+  out->nonfinite = nonfinite;
+  int rc = read_flag(L);
+  if (rc != LATTICE_OK) return rc;
+  if (nonfinite)
+    return set_err(L, LATTICE_ENONFINITE, "moments are not finite");
+  return LATTICE_OK;
+}
+
+int lattice_density(lattice_t* L, const void* f, double dt, double* rho) {
+  if (!L) return LATTICE_EINVAL;
+  L->msg[0] = 0;
+  if (!f || !rho || !(dt > 0.0) || !isfinite(dt))
+    return set_err(L, LATTICE_EINVAL, "bad density arguments");
+  const lattice_desc& d = L->d;
+  const double dv = (double)d.vstride * d.dx / dt;
+  const double dvd = d.dim == 1 ? dv : dv * dv;
+  HIPCHK(L, lat::launch_density(f, L->sites, (int)L->nplanes,
+                                d.dtype == LATTICE_F64, dvd, rho, L->stream));
+  return LATTICE_OK;
+}
+
+int lattice_stability(lattice_t* L, const void* u, int64_t n_u_slices,
+                      double tau_p, double kappa, double dt, double* out) {
+  if (!L) return LATTICE_EINVAL;
+  L->msg[0] = 0;
+  if (!u || !out || n_u_slices < 1 || !(dt > 0.0) || !(tau_p > 0.0) ||
+      !(kappa >= 0.0))
+    return set_err(L, LATTICE_EINVAL, "bad stability arguments");
+  const lattice_desc& d = L->d;
+  const double dv = (double)d.vstride * d.dx / dt;
+  const double vmax = ((d.nv - 1) / 2) * dv;
+  const double dts = dt / d.nsub;
+  HIPCHK(L, lat::launch_absmax(u, n_u_slices * d.dim * L->sites,
+                               d.dtype == LATTICE_F64, L->red, L->stream));
+  HIPCHK(L, hipMemcpyAsync(L->host_red, L->red, sizeof(double),
+                           hipMemcpyDeviceToHost, L->stream));
+  HIPCHK(L, hipStreamSynchronize(L->stream));
+  const double umax = L->host_red[0];
+  out[0] = (dts / dv) * (umax + vmax) / tau_p;
+  out[1] = kappa * dts / (dv * dv);
+  return LATTICE_OK;
+}
+
+int lattice_copy_state(lattice_t* L, void* dst, const void* src) {
+  if (!L) return LATTICE_EINVAL;
+  if (!dst || !src) return set_err(L, LATTICE_EINVAL, "NULL pointer");
+  HIPCHK(L, lat::launch_copy(dst, src, L->cells * (int64_t)L->elem,
+                             L->stream));
+  return LATTICE_OK;
+}
+
+int lattice_sync(lattice_t* L) {
+  if (!L) return LATTICE_EINVAL;
+  L->msg[0] = 0;
+  HIPCHK(L, hipStreamSynchronize(L->stream));
+  return read_flag(L);
+}
+
+int lattice_profile(lattice_t* L, int enable) {
+  if (!L) return LATTICE_EINVAL;
+  HIPCHK(L, hipStreamSynchronize(L->stream));
+  L->ev_used = 0;
+  L->prof_ms = 0.0;
+  L->prof_launches = 0;
+  L->prof = enable != 0;
+  return LATTICE_OK;
+}
+
+int lattice_profile_read(lattice_t* L, double* total_ms, int64_t* launches) {
+  if (!L || !total_ms || !launches) return LATTICE_EINVAL;
+  HIPCHK(L, hipStreamSynchronize(L->stream));
+  HIPCHK(L, prof_drain(L));
+  *total_ms = L->prof_ms;
+  *launches = L->prof_launches;
+  return LATTICE_OK;
+}
+
+int lattice_destroy(lattice_t* L) {
+  if (!L) return LATTICE_OK;
+  int rc = LATTICE_OK;
+  if (hipStreamSynchronize(L->stream) != hipSuccess) rc = LATTICE_EHIP;
+  if (L->scratch) (void)hipFree(L->scratch);
+  if (L->flag) (void)hipFree(L->flag);
+  if (L->plane_sums) (void)hipFree(L->plane_sums);
+  if (L->red) (void)hipFree(L->red);
+  if (L->host_red) (void)hipHostFree(L->host_red);
+  for (hipEvent_t e : L->ev) (void)hipEventDestroy(e);
+  delete L;
+  return rc;
+}
+
+const char* lattice_strerror(int code) {
+  switch (code) {
+    case LATTICE_OK: return "ok";
+    case LATTICE_EINVAL: return "invalid argument";
+    case LATTICE_ECFL: return "drift CFL condition (Eq. 3) violated";
+    case LATTICE_EDIFF: return "diffusion stability kappa dt/dv^2 < 1/2 violated";
+    case LATTICE_EHIP: return "HIP runtime error";
+    case LATTICE_ENOMEM: return "out of device memory";
+    case LATTICE_ENONFINITE: return "non-finite moments";
+    case LATTICE_ENOTSUP: return "no kernel compiled for this lattice";
+    default: return "unknown error";
+  }
+}
+
+const char* lattice_last_error(const lattice_t* L) { return L ? L->msg : ""; }
+
+}  // extern "C"

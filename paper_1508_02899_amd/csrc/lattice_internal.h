@@ -1,0 +1,57 @@
+// lattice_internal.h -- launch interfaces between the C-ABI host code and
+// the HIP kernels of the phase-space lattice library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lat {
+
+// One streaming + collision pass over the whole lattice (Sec. 2 of the
+// paper: exact streaming, then drift, then diffusion).  shift = 0 gives a
+// collision-only pass (used for the extra sub-steps when nsub > 1).
+struct StepArgs {
+  const void* fin;   // state before the pass
+  void* fout;        // state after the pass (distinct from fin)
+  const void* u;     // flow slice for this pass: [dim][ny][nx]
+  const int* flag;   // sticky device flag: nonzero -> pass is a no-op
+  int64_t nx, ny;
+  int nv;
+  int shift;         // cells moved per velocity index (vstride or 0)
+  int nsub_inline;   // 1D only: collision sub-steps done inside the pass
+  double alpha_scale;  // dt_s / (dv tau_p): drift of cell j in cell widths
+  double beta;         // dt_s / tau_p       is alpha_scale*u - beta*(j-h)
+  double D;            // kappa dt_s / dv^2
+  int koren;
+  int f64;
+};
+
+// Which velocity lattices have a compiled kernel.
+bool step1d_supported(int nv, int f64);
+bool step2d_supported(int nv, int f64);
+
+hipError_t launch_step1d(const StepArgs& a, hipStream_t s);
+hipError_t launch_step2d(const StepArgs& a, hipStream_t s);
+
+// Sticky CFL / finiteness check of the u slices: sets flag |= 1 when some
+// |u| exceeds umax_ok (strict: |u| >= umax_ok) or is not finite.
+hipError_t launch_cfl_check(const void* u, int64_t n, double umax_ok,
+                            int strict, int f64, int* flag, hipStream_t s);
+// max |u| over n values into *out (FP64 on device, reset inside).
+hipError_t launch_absmax(const void* u, int64_t n, int f64, double* out,
+                         hipStream_t s);
+
+// FP64 sums of every velocity plane (plane_sums[nplanes]) followed by the
+// weighted combination into out[6] = {M, Px, Py, Qx, Qy, variance}.
+hipError_t launch_moments(const void* f, int64_t sites, int nv, int dim,
+                          int f64, double w, double dv, double* plane_sums,
+                          double* out, hipStream_t s);
+// rho[site] = dvd * sum_j f[j][site] in FP64.
+hipError_t launch_density(const void* f, int64_t sites, int nplanes, int f64,
+                          double dvd, double* rho, hipStream_t s);
+
+hipError_t launch_copy(void* dst, const void* src, int64_t bytes,
+                       hipStream_t s);
+hipError_t launch_clear_flag(int* flag, hipStream_t s);
+
+}  // namespace lat

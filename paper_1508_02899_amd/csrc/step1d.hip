@@ -1,0 +1,147 @@
+// step1d.hip -- fused streaming + collision pass for 1D lattices (gfx950).
+//
+// One lane owns one spatial site and holds that site's whole velocity
+// column (capacity CAP >= nv, runtime nv) in registers:
+//   1. pull streaming (Sec. 2 of the paper): cell j of site x comes from
+//      site x - shift*(j-h); for a fixed j the lanes of a wavefront read
+//      consecutive addresses, so every load is one coalesced 256-byte run;
+//   2. nsub_inline times: drift (Eq. 5 force at cell centres, upwind or
+//      Koren-limited split fluxes, zero flux at the two outer faces), then
+//      diffusion (finite-difference face fluxes, Eq. 4);
+//   3. coalesced stores of the column to the output state.
+// Each state element is read once and written once per pass.
+#include "device_common.h"
+#include "lattice_internal.h"
+
+namespace lat {
+namespace {
+
+template <typename T, int CAP, bool KOREN>
+__global__ __launch_bounds__(256) void k_step1d(
+    const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict__ u,
+    const int* __restrict__ flag, int nx, int nv, int h, int step_mod,
+    int init_off, int nsub, T alpha_scale, T beta, T D, int nblocks) {
+  if (*flag != 0) return;
+  const int b = xcd_remap(blockIdx.x, nblocks);
+  const int x = b * 256 + (int)threadIdx.x;
+  if (x >= nx) return;
+
+  // ---- 1. pull streaming: source site of cell j is (x - shift*(j-h)) mod nx
+  T c[CAP];
+  int xs = x + init_off;  // (x + shift*h) mod nx
+  if (xs >= nx) xs -= nx;
+#pragma unroll
+  for (int j = 0; j < CAP; ++j) {
+    if (j < nv) {
+      c[j] = fin[(size_t)j * nx + xs];
+      xs -= step_mod;
+      if (xs < 0) xs += nx;
+    } else {
+      c[j] = T(0);
+    }
+  }
+
+  const T alpha = u[x] * alpha_scale;
+  for (int sub = 0; sub < nsub; ++sub) {
+    // ---- 2a. drift: split fluxes g+ = max(nu,0) c, g- = min(nu,0) c with
+    // nu_j = alpha - beta*(j-h).  Faces k = 1..nv-1 (cells k-1 | k) are
+    // visited in order with a sliding window of g values, and cell k-1 is
+    // updated as soon as its right face is known; faces 0 and nv carry no
+    // flux, cells past nv are empty.
+    T gpm2 = T(0), gpm1, gpk, gmm1, gmk, gmp1;
+    {
+      const T nu0 = alpha - beta * (T)(0 - h);
+      gpm1 = pos(nu0) * c[0];
+      gmm1 = neg(nu0) * c[0];
+      const T nu1 = alpha - beta * (T)(1 - h);
+      gpk = pos(nu1) * c[1];
+      gmk = neg(nu1) * c[1];
+    }
+    T Fprev = T(0);  // face k-1
+#pragma unroll
+    for (int k = 1; k <= CAP; ++k) {
+      T cnext = T(0);
+      if (k + 1 < CAP) cnext = c[k + 1];
+      const T nun = alpha - beta * (T)(k + 1 - h);
+      gmp1 = neg(nun) * cnext;
+      const T gpn = pos(nun) * cnext;
+      T fl = gpm1 + gmk;
+      if (KOREN)
+        fl += koren(gpk - gpm1, gpm1 - gpm2) + koren(gmm1 - gmk, gmk - gmp1);
+      fl = (k < nv) ? fl : T(0);  // face nv and beyond: zero flux
+      c[k - 1] = c[k - 1] - (fl - Fprev);
+      Fprev = fl;
+      gpm2 = gpm1;
+      gpm1 = gpk;
+      gpk = gpn;
+      gmm1 = gmk;
+      gmk = gmp1;
+    }
+
+    // ---- 2b. diffusion: face flux D (c_{k-1} - c_k), k = 1..nv-1
+    T dprev = T(0);
+    T cprev = c[0];
+#pragma unroll
+    for (int k = 1; k <= CAP; ++k) {
+      const T ck = k < CAP ? c[k] : T(0);
+      const T del = (k < nv) ? (cprev - ck) : T(0);
+      c[k - 1] = cprev + D * (dprev - del);
+      dprev = del;
+      cprev = ck;
+    }
+  }
+
+  // ---- 3. store
+#pragma unroll
+  for (int j = 0; j < CAP; ++j)
+    if (j < nv) fout[(size_t)j * nx + x] = c[j];
+}
+
+template <typename T, int CAP>
+hipError_t launch_cap(const StepArgs& a, hipStream_t s) {
+  const int nx = (int)a.nx;
+  const int nblocks = (nx + 255) / 256;
+  const int h = (a.nv - 1) / 2;
+  const int step_mod = a.shift % nx;
+  const int init_off = (int)(((int64_t)a.shift * h) % nx);
+  const T as = (T)a.alpha_scale, be = (T)a.beta, D = (T)a.D;
+  if (a.koren)
+    hipLaunchKernelGGL((k_step1d<T, CAP, true>), dim3(nblocks), dim3(256), 0,
+                       s, (const T*)a.fin, (T*)a.fout, (const T*)a.u, a.flag,
+                       nx, a.nv, h, step_mod, init_off, a.nsub_inline, as, be,
+                       D, nblocks);
+  else
+    hipLaunchKernelGGL((k_step1d<T, CAP, false>), dim3(nblocks), dim3(256), 0,
+                       s, (const T*)a.fin, (T*)a.fout, (const T*)a.u, a.flag,
+                       nx, a.nv, h, step_mod, init_off, a.nsub_inline, as, be,
+                       D, nblocks);
+  return hipGetLastError();
+}
+
+hipError_t launch_f32(const StepArgs& a, hipStream_t s) {
+  if (a.nv <= 9) return launch_cap<float, 9>(a, s);
+  if (a.nv <= 17) return launch_cap<float, 17>(a, s);
+  if (a.nv <= 33) return launch_cap<float, 33>(a, s);
+  if (a.nv <= 65) return launch_cap<float, 65>(a, s);
+  return launch_cap<float, 129>(a, s);
+}
+
+hipError_t launch_f64(const StepArgs& a, hipStream_t s) {
+  if (a.nv <= 9) return launch_cap<double, 9>(a, s);
+  if (a.nv <= 17) return launch_cap<double, 17>(a, s);
+  if (a.nv <= 33) return launch_cap<double, 33>(a, s);
+  return launch_cap<double, 65>(a, s);
+}
+
+}  // namespace
+
+bool step1d_supported(int nv, int f64) {
+  return nv >= 3 && (nv & 1) && nv <= (f64 ? 65 : 129);
+}
+
+hipError_t launch_step1d(const StepArgs& a, hipStream_t s) {
+  if (!step1d_supported(a.nv, a.f64) || a.nx < 1) return hipErrorInvalidValue;
+  return a.f64 ? launch_f64(a, s) : launch_f32(a, s);
+}
+
+}  // namespace lat

@@ -1,0 +1,11 @@
+// step2d_f32d.hip -- FP32 2D pass instantiation for nv = 65.
+#include "step2d.h"
+
+namespace lat {
+hipError_t step2d_f32_d(const StepArgs& a, hipStream_t s) {
+  switch (a.nv) {
+    case 65: return launch_step2d_nv<float, 65, 4>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+}  // namespace lat

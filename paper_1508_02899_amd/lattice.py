@@ -1,0 +1,322 @@
+"""Python binding of the C-ABI lattice library (liblattice.so).
+
+Argument marshalling only: every step of the lattice update runs in the
+HIP kernels behind ``include/lattice.h``.  PyTorch supplies device memory
+and the current HIP stream.  The library must have been built
+(``python -m paper_1508_02899_amd.build`` or ``__graft_entry__.build()``);
+importing this module without it raises ``LatticeLibraryMissing``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblattice.so")
+
+UPWIND, KOREN = 0, 1
+F32, F64 = 0, 1
+SCHEMES = {"upwind": UPWIND, "koren": KOREN}
+
+OK, EINVAL, ECFL, EDIFF, EHIP, ENOMEM, ENONFINITE, ENOTSUP = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+
+# every symbol declared in include/lattice.h
+EXPORTS = (
+    "lattice_desc_default", "lattice_velocity", "lattice_init", "lattice_step",
+    "lattice_moments", "lattice_density", "lattice_stability",
+    "lattice_copy_state", "lattice_sync", "lattice_profile",
+    "lattice_profile_read", "lattice_destroy", "lattice_strerror",
+    "lattice_last_error",
+)
+
+
+class LatticeLibraryMissing(RuntimeError):
+    pass
+
+
+class LatticeError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"lattice error {code}: {msg}")
+        self.code = code
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32),
+        ("nx", ctypes.c_int64),
+        ("ny", ctypes.c_int64),
+        ("nv", ctypes.c_int32),
+        ("vstride", ctypes.c_int32),
+        ("dx", ctypes.c_double),
+        ("scheme", ctypes.c_int32),
+        ("dtype", ctypes.c_int32),
+        ("nsub", ctypes.c_int32),
+        ("u_hold", ctypes.c_int64),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class Moments(ctypes.Structure):
+    _fields_ = [
+        ("mass", ctypes.c_double),
+        ("momentum", ctypes.c_double * 2),
+        ("second_moment", ctypes.c_double * 2),
+        ("variance", ctypes.c_double),
+        ("nonfinite", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load liblattice.so (fails loudly when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise LatticeLibraryMissing(
+            f"{path} not found: build the HIP library first "
+            "(python -m paper_1508_02899_amd.build)")
+    L = ctypes.CDLL(path)
+    vp, i64, dbl, i32 = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_double,
+                         ctypes.c_int)
+    pdesc = ctypes.POINTER(Desc)
+    L.lattice_desc_default.argtypes = [pdesc]
+    L.lattice_velocity.argtypes = [pdesc, dbl, ctypes.POINTER(dbl),
+                                   ctypes.POINTER(dbl)]
+    L.lattice_init.argtypes = [pdesc, ctypes.POINTER(vp)]
+    L.lattice_step.argtypes = [vp, vp, vp, i64, dbl, dbl, dbl, i64]
+    L.lattice_moments.argtypes = [vp, vp, dbl, ctypes.POINTER(Moments)]
+    L.lattice_density.argtypes = [vp, vp, dbl, vp]
+    L.lattice_stability.argtypes = [vp, vp, i64, dbl, dbl, dbl,
+                                    ctypes.POINTER(dbl)]
+    L.lattice_copy_state.argtypes = [vp, vp, vp]
+    L.lattice_sync.argtypes = [vp]
+    L.lattice_profile.argtypes = [vp, i32]
+    L.lattice_profile_read.argtypes = [vp, ctypes.POINTER(dbl),
+                                       ctypes.POINTER(i64)]
+    L.lattice_destroy.argtypes = [vp]
+    L.lattice_strerror.argtypes = [i32]
+    L.lattice_strerror.restype = ctypes.c_char_p
+    L.lattice_last_error.argtypes = [vp]
+    L.lattice_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        getattr(L, name)  # every declared entry point must be exported
+    _lib = L
+    return L
+
+
+@dataclass
+class LatticeSpec:
+    """Host-side description of a lattice (mirrors ``lattice_desc``)."""
+    dim: int
+    nx: int
+    nv: int
+    dx: float
+    ny: int = 1
+    vstride: int = 1
+    scheme: str = "koren"
+    dtype: str = "f32"
+    nsub: int = 1
+    u_hold: int = 0
+
+    def velocity(self, dt: float):
+        """(dv, Vmax) for time step dt: dv = vstride dx / dt, Vmax = h dv."""
+        dv = self.vstride * self.dx / dt
+        return dv, (self.nv - 1) // 2 * dv
+
+    @property
+    def nplanes(self) -> int:
+        return self.nv ** self.dim
+
+    @property
+    def state_shape(self):
+        if self.dim == 1:
+            return (self.nv, self.nx)
+        return (self.nv * self.nv, self.ny, self.nx)
+
+    def u_shape(self, slices: int):
+        if self.dim == 1:
+            return (slices, 1, self.nx)
+        return (slices, 2, self.ny, self.nx)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Lattice:
+    """Handle over ``lattice_t``: owns the library's scratch buffer.
+
+    ``f`` and ``u`` are CUDA (HIP) torch tensors in the library's layouts
+    (see ``include/lattice.h``); their dtype must match ``spec.dtype``.
+    Work is queued on ``stream`` (default: torch's current stream at
+    construction).
+    """
+
+    def __init__(self, spec: LatticeSpec, stream=None):
+        torch = _torch()
+        self._L = None
+        self.lib = load_library()
+        self.spec = spec
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        d = Desc()
+        self.lib.lattice_desc_default(ctypes.byref(d))
+        d.dim, d.nx, d.ny, d.nv = spec.dim, spec.nx, spec.ny, spec.nv
+        d.vstride, d.dx = spec.vstride, spec.dx
+        d.scheme = SCHEMES[spec.scheme]
+        d.dtype = F64 if spec.dtype == "f64" else F32
+        d.nsub, d.u_hold = spec.nsub, spec.u_hold
+        d.stream = ctypes.c_void_p(stream.cuda_stream)
+        h = ctypes.c_void_p()
+        self._check(self.lib.lattice_init(ctypes.byref(d), ctypes.byref(h)))
+        self._L = h
+        self.torch_dtype = torch.float64 if spec.dtype == "f64" else torch.float32
+
+    # -- helpers ---------------------------------------------------------
+    def _check(self, rc: int):
+        if rc != OK:
+            msg = self.lib.lattice_strerror(rc).decode()
+            if self._L is not None:
+                detail = self.lib.lattice_last_error(self._L).decode()
+                if detail:
+                    msg = f"{msg} ({detail})"
+            raise LatticeError(rc, msg)
+        return rc
+
+    def _tensor_ptr(self, t, shape=None, name="tensor"):
+        torch = _torch()
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError(f"{name} must be a CUDA tensor")
+        if t.dtype != self.torch_dtype:
+            raise TypeError(f"{name} dtype {t.dtype} != {self.torch_dtype}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if shape is not None and tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} shape {tuple(t.shape)} != {tuple(shape)}")
+        return ctypes.c_void_p(t.data_ptr())
+
+    # -- API -------------------------------------------------------------
+    def step(self, f, u, tau_p: float, kappa: float, dt: float, nsteps: int,
+             check: bool = True):
+        """Advance f in place by nsteps steps (asynchronous).
+
+        u holds one or more slices ([slices, dim, ny, nx] or
+        [slices, 1, nx] in 1D)."""
+        s = self.spec
+        fp = self._tensor_ptr(f, s.state_shape, "f")
+        per = s.dim * s.nx * (s.ny if s.dim == 2 else 1)
+        if u.numel() % per:
+            raise ValueError("u is not a whole number of slices")
+        up = self._tensor_ptr(u, None, "u")
+        rc = self.lib.lattice_step(self._L, fp, up, u.numel() // per,
+                                   float(tau_p), float(kappa), float(dt),
+                                   int(nsteps))
+        if check:
+            self._check(rc)
+        return rc
+
+    def moments(self, f, dt: float) -> dict:
+        """FP64 mass / momentum / second moment / variance (synchronous)."""
+        m = Moments()
+        rc = self.lib.lattice_moments(self._L, self._tensor_ptr(f, None, "f"),
+                                      float(dt), ctypes.byref(m))
+        out = {
+            "mass": m.mass,
+            "momentum": list(m.momentum)[: self.spec.dim],
+            "second_moment": list(m.second_moment)[: self.spec.dim],
+            "variance": m.variance,
+            "nonfinite": bool(m.nonfinite),
+            "rc": rc,
+        }
+        if rc not in (OK,):
+            self._check(rc)
+        return out
+
+    def density(self, f, dt: float):
+        """rho(x) = dv^dim sum_j f as a new FP64 CUDA tensor [ny, nx]."""
+        torch = _torch()
+        s = self.spec
+        rho = torch.empty((s.ny if s.dim == 2 else 1, s.nx),
+                          dtype=torch.float64, device=f.device)
+        self._check(self.lib.lattice_density(
+            self._L, self._tensor_ptr(f, None, "f"), float(dt),
+            ctypes.c_void_p(rho.data_ptr())))
+        return rho
+
+    def stability(self, u, tau_p: float, kappa: float, dt: float):
+        """(CFL of Eq. 3, kappa dt_s / dv^2 of Eq. 4) for the slices in u."""
+        s = self.spec
+        per = s.dim * s.nx * (s.ny if s.dim == 2 else 1)
+        out = (ctypes.c_double * 2)()
+        self._check(self.lib.lattice_stability(
+            self._L, self._tensor_ptr(u, None, "u"), u.numel() // per,
+            float(tau_p), float(kappa), float(dt), out))
+        return out[0], out[1]
+
+    def copy_state(self, dst, src):
+        self._check(self.lib.lattice_copy_state(
+            self._L, self._tensor_ptr(dst, self.spec.state_shape, "dst"),
+            self._tensor_ptr(src, self.spec.state_shape, "src")))
+
+    def sync(self, check: bool = True) -> int:
+        rc = self.lib.lattice_sync(self._L)
+        if check:
+            self._check(rc)
+        return rc
+
+    def profile(self, enable: bool):
+        self._check(self.lib.lattice_profile(self._L, 1 if enable else 0))
+
+    def profile_read(self):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        self._check(self.lib.lattice_profile_read(self._L, ctypes.byref(ms),
+                                                  ctypes.byref(n)))
+        return ms.value, n.value
+
+    def close(self):
+        if self._L is not None:
+            self.lib.lattice_destroy(self._L)
+            self._L = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def strerror(code: int) -> str:
+    return load_library().lattice_strerror(code).decode()
+
+
+def velocity(spec: LatticeSpec, dt: float):
+    """(dv, Vmax) computed by the library (host-only call)."""
+    L = load_library()
+    d = Desc()
+    L.lattice_desc_default(ctypes.byref(d))
+    d.dim, d.nx, d.ny, d.nv, d.vstride, d.dx = (spec.dim, spec.nx, spec.ny,
+                                                spec.nv, spec.vstride, spec.dx)
+    dv, vmax = ctypes.c_double(), ctypes.c_double()
+    rc = L.lattice_velocity(ctypes.byref(d), float(dt), ctypes.byref(dv),
+                            ctypes.byref(vmax))
+    if rc != OK:
+        raise LatticeError(rc, strerror(rc))
+    return dv.value, vmax.value
+
+
+__all__ = ["Lattice", "LatticeSpec", "LatticeError", "LatticeLibraryMissing",
+           "load_library", "strerror", "velocity", "EXPORTS"]

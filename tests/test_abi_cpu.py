@@ -1,0 +1,102 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/lattice.h declares, and its host-only entry points behave (no GPU
+call is made here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lattice.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lattice_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1508_02899_amd.lattice import load_library
+    return load_library()
+
+
+def test_header_declares_expected_api():
+    names = declared_functions()
+    for n in ["lattice_init", "lattice_step", "lattice_moments",
+              "lattice_destroy", "lattice_strerror"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_1508_02899_amd.lattice import EXPORTS
+    names = declared_functions()
+    assert sorted(EXPORTS) == names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_desc_default_and_velocity(lib):
+    from paper_1508_02899_amd.lattice import Desc
+    d = Desc()
+    assert lib.lattice_desc_default(ctypes.byref(d)) == 0
+    assert (d.dim, d.nv, d.vstride, d.nsub, d.scheme, d.dtype) == (1, 33, 1, 1,
+                                                                  1, 0)
+    # Sec. 3.2 geometry: L = 2 pi, nx = 2^(n+6), nv = 2^n + 1, dt = pi/64
+    # gives Vmax = 1
+    import math
+    n = 5
+    d.nx, d.nv, d.dx = 2 ** (n + 6), 2 ** n + 1, 2 * math.pi / 2 ** (n + 6)
+    dv, vmax = ctypes.c_double(), ctypes.c_double()
+    assert lib.lattice_velocity(ctypes.byref(d), math.pi / 64,
+                                ctypes.byref(dv), ctypes.byref(vmax)) == 0
+    assert vmax.value == pytest.approx(1.0, abs=1e-14)
+    assert dv.value == pytest.approx(2.0 / (d.nv - 1), abs=1e-14)
+    assert lib.lattice_velocity(ctypes.byref(d), -1.0, ctypes.byref(dv),
+                                ctypes.byref(vmax)) == -1
+
+
+@pytest.mark.parametrize("field,value", [("dim", 3), ("nv", 4), ("nv", 1),
+                                         ("nx", 0), ("dx", 0.0),
+                                         ("vstride", 0), ("nsub", 0),
+                                         ("scheme", 7), ("dtype", 2),
+                                         ("u_hold", -1)])
+def test_init_rejects_bad_descriptors_before_any_gpu_call(lib, field, value):
+    from paper_1508_02899_amd.lattice import Desc
+    d = Desc()
+    lib.lattice_desc_default(ctypes.byref(d))
+    d.nx = 64
+    setattr(d, field, value)
+    h = ctypes.c_void_p()
+    assert lib.lattice_init(ctypes.byref(d), ctypes.byref(h)) == -1
+    assert not h.value
+
+
+def test_init_reports_unsupported_2d_lattice(lib):
+    from paper_1508_02899_amd.lattice import Desc
+    d = Desc()
+    lib.lattice_desc_default(ctypes.byref(d))
+    d.dim, d.nx, d.ny, d.nv = 2, 8, 8, 23
+    h = ctypes.c_void_p()
+    assert lib.lattice_init(ctypes.byref(d), ctypes.byref(h)) == -7
+
+
+def test_strerror_and_null_handles(lib):
+    assert lib.lattice_strerror(-2).decode().startswith("drift CFL")
+    assert lib.lattice_strerror(12345).decode() == "unknown error"
+    assert lib.lattice_destroy(None) == 0
+    assert lib.lattice_step(None, None, None, 0, 1.0, 0.0, 1.0, 1) == -1
+    assert lib.lattice_last_error(None).decode() == ""
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    from paper_1508_02899_amd import lattice
+    saved = lattice._lib
+    lattice._lib = None
+    try:
+        with pytest.raises(lattice.LatticeLibraryMissing):
+            lattice.load_library(str(tmp_path / "nope.so"))
+    finally:
+        lattice._lib = saved

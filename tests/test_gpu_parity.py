@@ -1,0 +1,310 @@
+"""GPU parity: the HIP lattice update against the FP64 oracle.
+
+Same seeded inputs on both sides (the oracle gets the FP32-rounded values
+cast to FP64).  Bounds: relative L2 <= 1e-5 for FP32 state, <= 1e-12 for
+FP64 state, bit-exact for pure streaming.  Sizes span several tiles and a
+ragged tail (nx not a multiple of the 256-lane block or of the 2D
+wavefront tile).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from helpers import (FP32_REL_L2, FP64_REL_L2, make_case, rel_l2, run_gpu,
+                     run_oracle, say)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("nv", [3, 5, 9, 17, 33, 65, 129])
+@pytest.mark.parametrize("scheme", ["koren", "upwind"])
+def test_1d_f32_parity(nv, scheme):
+    say(f"1d f32 nv={nv} {scheme}")
+    f0, u, p = make_case(1, 300, nv, seed=nv, scheme=scheme)
+    got = run_gpu(f0, u, p, 12)
+    want = run_oracle(f0, u, p, 12)
+    err = rel_l2(got, want)
+    say("  rel L2", err)
+    assert err <= FP32_REL_L2
+
+
+@pytest.mark.parametrize("nv", [3, 9, 33, 65])
+@pytest.mark.parametrize("scheme", ["koren", "upwind"])
+def test_1d_f64_parity(nv, scheme):
+    say(f"1d f64 nv={nv} {scheme}")
+    f0, u, p = make_case(1, 257, nv, seed=100 + nv, dtype="f64", scheme=scheme)
+    got = run_gpu(f0, u, p, 10, dtype="f64")
+    want = run_oracle(f0, u, p, 10)
+    assert rel_l2(got, want) <= FP64_REL_L2
+
+
+def test_1d_f64_config1_shape_full_run():
+    """1D periodic 256 x 33 in FP64, random 8-mode flow renewed every 50
+    steps (u_hold = 50), St = 1, kappa = 1e-3, 1000 steps, Koren."""
+    from paper_1508_02899_amd import inputs
+    say("1d f64 256x33, 1000 steps, u_hold 50")
+    nx, nv, L = 256, 33, 2 * math.pi
+    nsteps, hold = 1000, 50
+    u = inputs.flow1d(nx, L, nsteps // hold, modes=8, spectrum="k-1",
+                      renew=hold, seed=inputs.seed_for(1), dtype=np.float64)
+    tau_p = 1.0 * L  # St = tau_p u_rms / L = 1
+    vmax = 5.0
+    h = (nv - 1) // 2
+    dv = vmax / h
+    dx = L / nx
+    dt = dx / dv
+    f0 = inputs.gaussian_ic(1, nx, nv, dx, dv, dtype=np.float64)
+    p = dict(dim=1, dx=dx, dt=dt, tau_p=tau_p, kappa=1e-3, s=1, nsub=1,
+             scheme="koren")
+    got = run_gpu(f0, u, p, nsteps, dtype="f64", u_hold=hold)
+    want = run_oracle(f0, u, p, nsteps, u_hold=hold)
+    err = rel_l2(got, want)
+    say("  rel L2", err)
+    assert err <= FP64_REL_L2
+
+
+@pytest.mark.parametrize("nv", [3, 5, 7, 9, 11, 13, 15, 17, 19, 21, 25, 33])
+def test_2d_f32_parity_koren(nv):
+    say(f"2d f32 nv={nv} koren")
+    f0, u, p = make_case(2, 70, nv, ny=9, seed=200 + nv)
+    got = run_gpu(f0, u, p, 4)
+    want = run_oracle(f0, u, p, 4)
+    err = rel_l2(got, want)
+    say("  rel L2", err)
+    assert err <= FP32_REL_L2
+
+
+@pytest.mark.parametrize("nv", [5, 17, 33])
+def test_2d_f32_parity_upwind(nv):
+    say(f"2d f32 nv={nv} upwind")
+    f0, u, p = make_case(2, 45, nv, ny=7, seed=300 + nv, scheme="upwind")
+    got = run_gpu(f0, u, p, 4)
+    want = run_oracle(f0, u, p, 4)
+    assert rel_l2(got, want) <= FP32_REL_L2
+
+
+def test_2d_f32_parity_nv65():
+    say("2d f32 nv=65 koren")
+    f0, u, p = make_case(2, 37, 65, ny=5, seed=465)
+    got = run_gpu(f0, u, p, 3)
+    want = run_oracle(f0, u, p, 3)
+    err = rel_l2(got, want)
+    say("  rel L2", err)
+    assert err <= FP32_REL_L2
+
+
+@pytest.mark.parametrize("nv", [3, 5, 9, 17, 33])
+def test_2d_f64_parity(nv):
+    say(f"2d f64 nv={nv}")
+    f0, u, p = make_case(2, 40, nv, ny=6, seed=500 + nv, dtype="f64")
+    got = run_gpu(f0, u, p, 3, dtype="f64")
+    want = run_oracle(f0, u, p, 3)
+    assert rel_l2(got, want) <= FP64_REL_L2
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_nsub_stride_and_u_hold(dim):
+    """nsub = 3 collision sub-steps, velocity stride 4 (coarse lattice),
+    three u slices held two steps each."""
+    say(f"nsub/stride/u_hold dim={dim}")
+    nv = 9
+    if dim == 1:
+        f0, u, p = make_case(1, 130, nv, seed=7, slices=3, s=4, nsub=3)
+    else:
+        f0, u, p = make_case(2, 50, nv, ny=11, seed=8, slices=3, s=4, nsub=3)
+    got = run_gpu(f0, u, p, 6, u_hold=2)
+    want = run_oracle(f0, u, p, 6, u_hold=2)
+    err = rel_l2(got, want)
+    say("  rel L2", err)
+    assert err <= FP32_REL_L2
+
+
+@pytest.mark.parametrize("dim,nv", [(1, 33), (1, 129), (2, 9), (2, 33)])
+def test_pure_streaming_bit_exact(dim, nv):
+    """tau_p = inf and kappa = 0: exact periodic permutation (np.roll)."""
+    say(f"streaming dim={dim} nv={nv}")
+    if dim == 1:
+        f0, u, p = make_case(1, 200, nv, seed=9)
+    else:
+        f0, u, p = make_case(2, 33, nv, ny=10, seed=10)
+    p = dict(p, tau_p=math.inf, kappa=0.0)
+    nsteps = 5
+    got = run_gpu(f0, u, p, nsteps)
+    h = (nv - 1) // 2
+    if dim == 1:
+        want = np.stack([np.roll(f0[j], (j - h) * nsteps) for j in range(nv)])
+    else:
+        want = np.empty_like(f0)
+        for jy in range(nv):
+            for jx in range(nv):
+                want[jy * nv + jx] = np.roll(
+                    f0[jy * nv + jx], ((jy - h) * nsteps, (jx - h) * nsteps),
+                    axis=(0, 1))
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_translation_and_determinism_bit_exact(dim):
+    """Rolling f and u by (3, 5) sites rolls the GPU result exactly, and two
+    runs are bit-identical (tile placement does not change arithmetic)."""
+    nv = 33 if dim == 1 else 17
+    if dim == 1:
+        f0, u, p = make_case(1, 600, nv, seed=11)
+        sh, ax, axu = 5, (1,), (2,)
+        shift = (sh,)
+    else:
+        f0, u, p = make_case(2, 96, nv, ny=8, seed=12)
+        shift, ax, axu = (3, 5), (1, 2), (2, 3)
+    a = run_gpu(f0, u, p, 5)
+    b = run_gpu(f0, u, p, 5)
+    assert np.array_equal(a, b)
+    c = run_gpu(np.ascontiguousarray(np.roll(f0, shift, axis=ax)),
+                np.ascontiguousarray(np.roll(u, shift, axis=axu)), p, 5)
+    assert np.array_equal(np.roll(a, shift, axis=ax), c)
+
+
+@pytest.mark.parametrize("dim,dtype", [(1, "f64"), (2, "f64"), (1, "f32"),
+                                       (2, "f32")])
+def test_moments_and_mass_conservation(dim, dtype):
+    """FP64 moments on the GPU equal the oracle's moments of the same state;
+    mass is conserved to 1e-12 (FP64 state) / 1e-6 (FP32 state)."""
+    import torch
+    import oracle
+    from paper_1508_02899_amd import Lattice
+    from helpers import spec_for
+    if dim == 1:
+        f0, u, p = make_case(1, 512, 33, seed=13, dtype=dtype)
+    else:
+        f0, u, p = make_case(2, 64, 17, ny=16, seed=14, dtype=dtype)
+    lat = Lattice(spec_for(f0, p, dtype))
+    f = torch.from_numpy(f0).cuda()
+    ut = torch.from_numpy(u).cuda()
+    m0 = lat.moments(f, p["dt"])
+    o0 = oracle.moments(f0, dim=dim, dx=p["dx"], dt=p["dt"])
+    assert m0["mass"] == pytest.approx(o0["mass"], rel=1e-13)
+    for k in range(dim):
+        assert m0["momentum"][k] == pytest.approx(o0["momentum"][k], rel=1e-11,
+                                                  abs=1e-13)
+        assert m0["second_moment"][k] == pytest.approx(o0["second_moment"][k],
+                                                       rel=1e-12)
+    assert m0["variance"] == pytest.approx(o0["variance"], rel=1e-11)
+    lat.step(f, ut, p["tau_p"], p["kappa"], p["dt"], 40)
+    m1 = lat.moments(f, p["dt"])
+    drift = abs(m1["mass"] - m0["mass"]) / m0["mass"]
+    say(f"  mass drift {dtype} dim={dim}: {drift:.3e}")
+    assert drift <= (1e-12 if dtype == "f64" else 1e-6)
+    assert float(f.min()) >= -1e-7 * float(f.max())
+    lat.close()
+
+
+def test_density_matches_velocity_sum():
+    import torch
+    from paper_1508_02899_amd import Lattice
+    from helpers import spec_for
+    f0, u, p = make_case(2, 50, 9, ny=12, seed=15, dtype="f64")
+    lat = Lattice(spec_for(f0, p, "f64"))
+    rho = lat.density(torch.from_numpy(f0).cuda(), p["dt"]).cpu().numpy()
+    dv = p["dx"] / p["dt"]
+    np.testing.assert_allclose(rho, f0.sum(axis=0) * dv * dv, rtol=1e-14)
+    lat.close()
+
+
+def test_cfl_violation_is_sticky_and_leaves_f():
+    """|u| past the bound of Eq. 3: flag set on the device, the call's
+    steps are no-ops, lattice_sync reports ECFL once and clears it."""
+    import torch
+    from paper_1508_02899_amd import Lattice, LatticeError
+    from paper_1508_02899_amd.lattice import ECFL
+    from helpers import spec_for
+    f0, u, p = make_case(1, 256, 17, seed=16)
+    lat = Lattice(spec_for(f0, p, "f32"))
+    f = torch.from_numpy(f0).cuda()
+    bad = torch.from_numpy(u * 50.0).cuda()
+    lat.step(f, bad, p["tau_p"], p["kappa"], p["dt"], 3)
+    assert lat.sync(check=False) == ECFL
+    assert np.array_equal(f.cpu().numpy(), f0)
+    assert lat.sync(check=False) == 0  # cleared
+    nan = torch.from_numpy(u).cuda()
+    nan[0, 0, 5] = float("nan")
+    lat.step(f, nan, p["tau_p"], p["kappa"], p["dt"], 2)
+    with pytest.raises(LatticeError):
+        lat.sync()
+    # a good call afterwards works
+    lat.step(f, torch.from_numpy(u).cuda(), p["tau_p"], p["kappa"], p["dt"], 2)
+    lat.sync()
+    lat.close()
+
+
+def test_host_side_errors():
+    import torch
+    from paper_1508_02899_amd import Lattice, LatticeError
+    from paper_1508_02899_amd.lattice import EDIFF, EINVAL, ECFL
+    from helpers import spec_for
+    f0, u, p = make_case(1, 64, 9, seed=17)
+    lat = Lattice(spec_for(f0, p, "f32"))
+    f = torch.from_numpy(f0).cuda()
+    ut = torch.from_numpy(u).cuda()
+    dv = p["dx"] / p["dt"]
+    with pytest.raises(LatticeError) as e:
+        lat.step(f, ut, p["tau_p"], 0.6 * dv * dv / p["dt"], p["dt"], 1)
+    assert e.value.code == EDIFF
+    with pytest.raises(LatticeError) as e:
+        lat.step(f, ut, -1.0, p["kappa"], p["dt"], 1)
+    assert e.value.code == EINVAL
+    with pytest.raises(LatticeError) as e:  # Vmax alone violates CFL
+        lat.step(f, ut, 1e-6, p["kappa"], p["dt"], 1)
+    assert e.value.code == ECFL
+    with pytest.raises(LatticeError) as e:  # not enough u slices
+        from paper_1508_02899_amd import LatticeSpec
+        lat2 = Lattice(LatticeSpec(dim=1, nx=64, nv=9, dx=p["dx"], u_hold=1))
+        lat2.step(f, ut, p["tau_p"], p["kappa"], p["dt"], 3)
+    assert e.value.code == EINVAL
+    lat.step(f, ut, p["tau_p"], p["kappa"], p["dt"], 0)  # no-op
+    assert np.array_equal(f.cpu().numpy(), f0)
+    lat.close()
+
+
+def test_config3_full_size_sampled_sites():
+    """2D 512^2 x 33^2 FP32 (1.14 GB state), the bench launch: one step on
+    the GPU; 64 sampled sites (corners, edges, interior) recomputed one by
+    one by the oracle from their streamed velocity columns."""
+    import torch
+    import oracle
+    from paper_1508_02899_amd import Lattice, LatticeSpec, inputs
+    say("config-3 full size sampled parity")
+    n, nv, L = 512, 33, 2 * math.pi
+    h = (nv - 1) // 2
+    u = inputs.flow2d_streamfunction(n, L, 1, seed=inputs.seed_for(3))
+    vmax = 3.0
+    dv = vmax / h
+    dx = L / n
+    dt = dx / dv
+    tau_p = 2 * math.pi  # St = 1
+    p = dict(dim=2, dx=dx, dt=dt, tau_p=tau_p, kappa=1e-4, s=1, nsub=1,
+             scheme="koren")
+    rng = np.random.default_rng(16)
+    f0 = torch.rand((nv * nv, n, n), generator=torch.Generator().manual_seed(3),
+                    dtype=torch.float32)
+    lat = Lattice(LatticeSpec(dim=2, nx=n, ny=n, nv=nv, dx=dx))
+    fd = f0.cuda()
+    lat.step(fd, torch.from_numpy(u).cuda(), tau_p, p["kappa"], dt, 1)
+    lat.sync()
+    out = fd.cpu().numpy()
+    f0n = f0.numpy()
+    sites = [(0, 0), (0, n - 1), (n - 1, 0), (n - 1, n - 1), (5, 17), (511, 200)]
+    sites += [tuple(rng.integers(0, n, 2)) for _ in range(58)]
+    jy, jx = np.divmod(np.arange(nv * nv), nv)
+    worst = 0.0
+    for (y, x) in sites:
+        col = f0n[np.arange(nv * nv), (y - (jy - h)) % n, (x - (jx - h)) % n]
+        uu = u[:, :, y:y + 1, x:x + 1].astype(np.float64)
+        # a 1x1 periodic lattice: streaming is the identity, the oracle
+        # applies exactly the collision of this site
+        ref = oracle.step(col.reshape(nv * nv, 1, 1).astype(np.float64), uu,
+                          dim=2, dx=dx, tau_p=tau_p, kappa=p["kappa"], dt=dt,
+                          nsteps=1)
+        worst = max(worst, rel_l2(out[:, y, x], ref[:, 0, 0]))
+    say("  worst site rel L2", worst)
+    assert worst <= FP32_REL_L2
+    lat.close()
