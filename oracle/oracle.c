@@ -20,7 +20,7 @@
  *     D  finite-volume velocity diffusion kappa d_v^2 f (Eq. 4 bound),
  *   with zero flux through the outer faces of the velocity domain.
  *
- * Readings of points the paper leaves open (each is listed in the design doc):
+ * Readings of points the paper leaves open:
  *   - drift sign follows the particle equation (Eq. 5): mass drifts toward u;
  *   - dv = 2 Vmax / (nv - 1): cell centres span [-Vmax, Vmax] (Sec. 3.2 and
  *     the caption of Fig. 14 fix this; Sec. 2 prints 2 Vmax / nv);

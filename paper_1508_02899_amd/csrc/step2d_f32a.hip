@@ -8,7 +8,7 @@ hipError_t step2d_f32_a(const StepArgs& a, hipStream_t s) {
     case 5: return launch_step2d_nv<float, 5, 1>(a, s);
     case 7: return launch_step2d_nv<float, 7, 1>(a, s);
     case 9: return launch_step2d_nv<float, 9, 1>(a, s);
-    case 11: return launch_step2d_nv<float, 11, 1>(a, s);
+    case 11: return launch_step2d_nv<float, 11, 2>(a, s);
     default: return hipErrorInvalidValue;
   }
 }

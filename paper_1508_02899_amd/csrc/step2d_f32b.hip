@@ -4,11 +4,11 @@
 namespace lat {
 hipError_t step2d_f32_b(const StepArgs& a, hipStream_t s) {
   switch (a.nv) {
-    case 13: return launch_step2d_nv<float, 13, 1>(a, s);
-    case 15: return launch_step2d_nv<float, 15, 1>(a, s);
-    case 17: return launch_step2d_nv<float, 17, 1>(a, s);
+    case 13: return launch_step2d_nv<float, 13, 2>(a, s);
+    case 15: return launch_step2d_nv<float, 15, 2>(a, s);
+    case 17: return launch_step2d_nv<float, 17, 2>(a, s);
     case 19: return launch_step2d_nv<float, 19, 2>(a, s);
-    case 21: return launch_step2d_nv<float, 21, 2>(a, s);
+    case 21: return launch_step2d_nv<float, 21, 4>(a, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -4,7 +4,7 @@
 namespace lat {
 hipError_t step2d_f32_c(const StepArgs& a, hipStream_t s) {
   switch (a.nv) {
-    case 25: return launch_step2d_nv<float, 25, 2>(a, s);
+    case 25: return launch_step2d_nv<float, 25, 4>(a, s);
     case 33: return launch_step2d_nv<float, 33, 4>(a, s);
     default: return hipErrorInvalidValue;
   }

@@ -39,7 +39,7 @@ def test_1d_f64_parity(nv, scheme):
     assert rel_l2(got, want) <= FP64_REL_L2
 
 
-def test_1d_f64_config1_shape_full_run():
+def test_1d_f64_256x33_1000_steps_renewed_flow():
     """1D periodic 256 x 33 in FP64, random 8-mode flow renewed every 50
     steps (u_hold = 50), St = 1, kappa = 1e-3, 1000 steps, Koren."""
     from paper_1508_02899_amd import inputs
@@ -265,7 +265,7 @@ def test_host_side_errors():
     lat.close()
 
 
-def test_config3_full_size_sampled_sites():
+def test_2d_512x512_v33_full_size_sampled_sites():
     """2D 512^2 x 33^2 FP32 (1.14 GB state), the bench launch: one step on
     the GPU; 64 sampled sites (corners, edges, interior) recomputed one by
     one by the oracle from their streamed velocity columns."""
