@@ -201,6 +201,82 @@ const char* lattice_strerror(int code);
  * or "" ; valid until the next call on the handle. */
 const char* lattice_last_error(const lattice_t* L);
 
+
+/* ===================================================================== *
+ * Batched 1D lattices: many independent realizations (each with its own
+ * grid size, velocity lattice, time step, Stokes number, diffusivity and
+ * flow) advanced together.  Every member follows exactly the single-lattice
+ * update of lattice_step (Sec. 2, Eqs. 3-5), FP32 state.
+ *
+ * Packed layouts (device, FP32): member m's state occupies
+ * f[f_off[m] .. f_off[m] + nv_m*nx_m) in the layout [nv_m][nx_m]; its flow
+ * occupies u[u_off[m] .. u_off[m] + n_u_slices_m*nx_m) as [slices][nx_m].
+ * Offsets are assigned by lattice_batch_init in member order (query them
+ * with lattice_batch_layout).
+ *
+ * One lattice_batch_step call queues, per time step, one persistent kernel
+ * per velocity-capacity class (members with nv <= 9, 17, 33, 65, 129); the
+ * classes run on parallel streams (they touch disjoint memory).  With
+ * use_graph != 0 the per-step launches are captured once into a HIP graph
+ * of graph_steps steps and replayed.
+ * ===================================================================== */
+typedef struct lattice_batch lattice_batch_t;
+
+typedef struct {
+  int64_t nx;          /* sites (>= 1) */
+  int32_t nv;          /* odd, 3..129 */
+  double dx;           /* spatial spacing (> 0) */
+  double dt;           /* time step (> 0); dv = vstride dx / dt */
+  double tau_p;        /* > 0, may be +INFINITY */
+  double kappa;        /* >= 0; kappa dt / dv^2 < 1/2 (Eq. 4) */
+  int64_t u_hold;      /* steps per u slice; 0 = one slice */
+  int64_t n_u_slices;  /* slices stored for this member (>= 1) */
+} lattice_member_desc;
+
+/* Validate count members (all must satisfy Eq. 4 and have Vmax alone
+ * within the drift bound) and allocate the packed scratch state, the
+ * member table, the work lists and reduction buffers.  EINVAL, EDIFF, ECFL,
+ * ENOMEM, EHIP.  scheme: LATTICE_UPWIND / LATTICE_KOREN; stream: hipStream_t
+ * or NULL. */
+int lattice_batch_init(const lattice_member_desc* members, int32_t count,
+                       int32_t scheme, int32_t vstride, void* stream,
+                       lattice_batch_t** out);
+
+/* Packed offsets (host arrays of count elements, may be NULL) and totals. */
+int lattice_batch_layout(const lattice_batch_t* B, int64_t* f_off,
+                         int64_t* u_off, int64_t* total_cells,
+                         int64_t* total_u);
+
+/* Work decomposition of one capacity class (cap = 9, 17, 33, 65 or 129):
+ * block = lanes (= sites) per tile (64, 128 or 256); grid_per_cu = resident
+ * workgroups per compute unit of the persistent launch (1..16, or 0 = one
+ * workgroup per tile, not persistent).  Chosen by the autotuner; defaults
+ * 256 / 0.  EINVAL. */
+int lattice_batch_tune(lattice_batch_t* B, int32_t cap, int32_t block,
+                       int32_t grid_per_cu);
+
+/* Advance every member by nsteps (asynchronous).  u must hold, for each
+ * member, ceil(nsteps/u_hold) slices (1 if u_hold == 0).  The drift CFL of
+ * Eq. 3 is checked on the device per member; a violating member is frozen
+ * (its steps are no-ops) and reported by lattice_batch_sync.  use_graph:
+ * 0 = eager launches, else replay a HIP graph of graph_steps (even) steps.
+ * EINVAL, EHIP. */
+int lattice_batch_step(lattice_batch_t* B, float* f, const float* u,
+                       int64_t nsteps, int32_t use_graph,
+                       int32_t graph_steps);
+
+/* FP64 moments per member into out[count][6] = {mass, momentum,
+ * second moment, variance, 0, 0} (host), reduced on the GPU in a fixed
+ * order.  Synchronous.  EINVAL, EHIP. */
+int lattice_batch_moments(lattice_batch_t* B, const float* f, double* out);
+
+/* Wait; return ECFL if some member was frozen since the last report (its
+ * flag is copied to member_flags[count] when that is not NULL, and
+ * cleared), else 0 / EHIP. */
+int lattice_batch_sync(lattice_batch_t* B, int32_t* member_flags);
+
+int lattice_batch_destroy(lattice_batch_t* B);
+
 #ifdef __cplusplus
 }
 #endif

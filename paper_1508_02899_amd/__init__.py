@@ -5,5 +5,6 @@ arXiv:1508.02899 (Sec. 2) as hand-written HIP kernels for gfx950 behind the
 C ABI in ``include/lattice.h``; ``lattice`` is the Python binding and
 ``inputs`` the seeded synthetic flows and initial conditions.
 """
-from .lattice import (Lattice, LatticeError, LatticeLibraryMissing,  # noqa: F401
-                      LatticeSpec, load_library, strerror, velocity)
+from .lattice import (Batch, Lattice, LatticeError,  # noqa: F401
+                      LatticeLibraryMissing, LatticeSpec, Member,
+                      load_library, strerror, velocity)

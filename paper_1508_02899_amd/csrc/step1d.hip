@@ -10,7 +10,7 @@
 //      diffusion (finite-difference face fluxes, Eq. 4);
 //   3. coalesced stores of the column to the output state.
 // Each state element is read once and written once per pass.
-#include "device_common.h"
+#include "column1d.h"
 #include "lattice_internal.h"
 
 namespace lat {
@@ -25,76 +25,8 @@ __global__ __launch_bounds__(256) void k_step1d(
   const int b = xcd_remap(blockIdx.x, nblocks);
   const int x = b * 256 + (int)threadIdx.x;
   if (x >= nx) return;
-
-  // ---- 1. pull streaming: source site of cell j is (x - shift*(j-h)) mod nx
-  T c[CAP];
-  int xs = x + init_off;  // (x + shift*h) mod nx
-  if (xs >= nx) xs -= nx;
-#pragma unroll
-  for (int j = 0; j < CAP; ++j) {
-    if (j < nv) {
-      c[j] = fin[(size_t)j * nx + xs];
-      xs -= step_mod;
-      if (xs < 0) xs += nx;
-    } else {
-      c[j] = T(0);
-    }
-  }
-
-  const T alpha = u[x] * alpha_scale;
-  for (int sub = 0; sub < nsub; ++sub) {
-    // ---- 2a. drift: split fluxes g+ = max(nu,0) c, g- = min(nu,0) c with
-    // nu_j = alpha - beta*(j-h).  Faces k = 1..nv-1 (cells k-1 | k) are
-    // visited in order with a sliding window of g values, and cell k-1 is
-    // updated as soon as its right face is known; faces 0 and nv carry no
-    // flux, cells past nv are empty.
-    T gpm2 = T(0), gpm1, gpk, gmm1, gmk, gmp1;
-    {
-      const T nu0 = alpha - beta * (T)(0 - h);
-      gpm1 = pos(nu0) * c[0];
-      gmm1 = neg(nu0) * c[0];
-      const T nu1 = alpha - beta * (T)(1 - h);
-      gpk = pos(nu1) * c[1];
-      gmk = neg(nu1) * c[1];
-    }
-    T Fprev = T(0);  // face k-1
-#pragma unroll
-    for (int k = 1; k <= CAP; ++k) {
-      T cnext = T(0);
-      if (k + 1 < CAP) cnext = c[k + 1];
-      const T nun = alpha - beta * (T)(k + 1 - h);
-      gmp1 = neg(nun) * cnext;
-      const T gpn = pos(nun) * cnext;
-      T fl = gpm1 + gmk;
-      if (KOREN)
-        fl += koren(gpk - gpm1, gpm1 - gpm2) + koren(gmm1 - gmk, gmk - gmp1);
-      fl = (k < nv) ? fl : T(0);  // face nv and beyond: zero flux
-      c[k - 1] = c[k - 1] - (fl - Fprev);
-      Fprev = fl;
-      gpm2 = gpm1;
-      gpm1 = gpk;
-      gpk = gpn;
-      gmm1 = gmk;
-      gmk = gmp1;
-    }
-
-    // ---- 2b. diffusion: face flux D (c_{k-1} - c_k), k = 1..nv-1
-    T dprev = T(0);
-    T cprev = c[0];
-#pragma unroll
-    for (int k = 1; k <= CAP; ++k) {
-      const T ck = k < CAP ? c[k] : T(0);
-      const T del = (k < nv) ? (cprev - ck) : T(0);
-      c[k - 1] = cprev + D * (dprev - del);
-      dprev = del;
-      cprev = ck;
-    }
-  }
-
-  // ---- 3. store
-#pragma unroll
-  for (int j = 0; j < CAP; ++j)
-    if (j < nv) fout[(size_t)j * nx + x] = c[j];
+  column1d<T, CAP, KOREN>(fin, fout, x, nx, nv, h, step_mod, init_off, nsub,
+                          u[x] * alpha_scale, beta, D);
 }
 
 template <typename T, int CAP>

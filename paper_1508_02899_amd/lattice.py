@@ -28,7 +28,9 @@ EXPORTS = (
     "lattice_moments", "lattice_density", "lattice_stability",
     "lattice_copy_state", "lattice_sync", "lattice_profile",
     "lattice_profile_read", "lattice_destroy", "lattice_strerror",
-    "lattice_last_error",
+    "lattice_last_error", "lattice_batch_init", "lattice_batch_layout",
+    "lattice_batch_tune", "lattice_batch_step", "lattice_batch_moments",
+    "lattice_batch_sync", "lattice_batch_destroy",
 )
 
 
@@ -55,6 +57,19 @@ class Desc(ctypes.Structure):
         ("nsub", ctypes.c_int32),
         ("u_hold", ctypes.c_int64),
         ("stream", ctypes.c_void_p),
+    ]
+
+
+class MemberDesc(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int64),
+        ("nv", ctypes.c_int32),
+        ("dx", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("tau_p", ctypes.c_double),
+        ("kappa", ctypes.c_double),
+        ("u_hold", ctypes.c_int64),
+        ("n_u_slices", ctypes.c_int64),
     ]
 
 
@@ -103,6 +118,18 @@ def load_library(path: str = LIB_PATH):
     L.lattice_strerror.restype = ctypes.c_char_p
     L.lattice_last_error.argtypes = [vp]
     L.lattice_last_error.restype = ctypes.c_char_p
+    pmem = ctypes.POINTER(MemberDesc)
+    pi64 = ctypes.POINTER(i64)
+    L.lattice_batch_init.argtypes = [pmem, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_int32, vp, ctypes.POINTER(vp)]
+    L.lattice_batch_layout.argtypes = [vp, pi64, pi64, pi64, pi64]
+    L.lattice_batch_tune.argtypes = [vp, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_int32]
+    L.lattice_batch_step.argtypes = [vp, vp, vp, i64, ctypes.c_int32,
+                                     ctypes.c_int32]
+    L.lattice_batch_moments.argtypes = [vp, vp, ctypes.POINTER(dbl)]
+    L.lattice_batch_sync.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    L.lattice_batch_destroy.argtypes = [vp]
     for name in EXPORTS:
         getattr(L, name)  # every declared entry point must be exported
     _lib = L
@@ -299,6 +326,120 @@ class Lattice:
         self.close()
 
 
+@dataclass
+class Member:
+    """One realization of a batch (mirrors ``lattice_member_desc``)."""
+    nx: int
+    nv: int
+    dx: float
+    dt: float
+    tau_p: float
+    kappa: float
+    u_hold: int = 0
+    n_u_slices: int = 1
+
+
+class Batch:
+    """Handle over ``lattice_batch_t``: many independent 1D lattices (FP32)
+    packed in one state buffer and advanced together."""
+
+    CAPS = (9, 17, 33, 65, 129)
+
+    def __init__(self, members, scheme: str = "koren", vstride: int = 1,
+                 stream=None):
+        torch = _torch()
+        self._B = None
+        self.lib = load_library()
+        self.members = list(members)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        arr = (MemberDesc * len(self.members))()
+        for i, m in enumerate(self.members):
+            arr[i] = MemberDesc(m.nx, m.nv, m.dx, m.dt, m.tau_p, m.kappa,
+                                m.u_hold, m.n_u_slices)
+        h = ctypes.c_void_p()
+        rc = self.lib.lattice_batch_init(arr, len(self.members),
+                                         SCHEMES[scheme], vstride,
+                                         ctypes.c_void_p(stream.cuda_stream),
+                                         ctypes.byref(h))
+        if rc != OK:
+            raise LatticeError(rc, strerror(rc))
+        self._B = h
+        n = len(self.members)
+        fo = (ctypes.c_int64 * n)()
+        uo = (ctypes.c_int64 * n)()
+        tc, tu = ctypes.c_int64(), ctypes.c_int64()
+        self._check(self.lib.lattice_batch_layout(h, fo, uo, ctypes.byref(tc),
+                                                  ctypes.byref(tu)))
+        self.f_off = list(fo)
+        self.u_off = list(uo)
+        self.total_cells = tc.value
+        self.total_u = tu.value
+
+    def _check(self, rc):
+        if rc != OK:
+            raise LatticeError(rc, strerror(rc))
+        return rc
+
+    def pack_state(self, states):
+        """Concatenate per-member [nv, nx] arrays into one packed vector."""
+        import numpy as np
+        out = np.empty(self.total_cells, dtype=np.float32)
+        for m, o, a in zip(self.members, self.f_off, states):
+            out[o:o + m.nv * m.nx] = np.asarray(a, np.float32).ravel()
+        return out
+
+    def unpack_state(self, flat):
+        return [flat[o:o + m.nv * m.nx].reshape(m.nv, m.nx)
+                for m, o in zip(self.members, self.f_off)]
+
+    def pack_flow(self, flows):
+        import numpy as np
+        out = np.empty(self.total_u, dtype=np.float32)
+        for m, o, a in zip(self.members, self.u_off, flows):
+            out[o:o + m.n_u_slices * m.nx] = np.asarray(a, np.float32).ravel()
+        return out
+
+    def tune(self, cap: int, block: int, grid_per_cu: int):
+        self._check(self.lib.lattice_batch_tune(self._B, cap, block,
+                                                grid_per_cu))
+
+    def step(self, f, u, nsteps: int, graph_steps: int = 0):
+        """Advance every member by nsteps (asynchronous); graph_steps > 0
+        replays a captured HIP graph of that many (even) steps."""
+        self._check(self.lib.lattice_batch_step(
+            self._B, ctypes.c_void_p(f.data_ptr()),
+            ctypes.c_void_p(u.data_ptr()), int(nsteps),
+            1 if graph_steps else 0, int(graph_steps)))
+
+    def moments(self, f):
+        import numpy as np
+        out = (ctypes.c_double * (6 * len(self.members)))()
+        self._check(self.lib.lattice_batch_moments(
+            self._B, ctypes.c_void_p(f.data_ptr()), out))
+        return np.array(out).reshape(len(self.members), 6)
+
+    def sync(self, check: bool = True):
+        import numpy as np
+        fl = (ctypes.c_int32 * len(self.members))()
+        rc = self.lib.lattice_batch_sync(self._B, fl)
+        if check:
+            self._check(rc)
+        return rc, np.array(fl)
+
+    def close(self):
+        if self._B is not None:
+            self.lib.lattice_batch_destroy(self._B)
+            self._B = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def strerror(code: int) -> str:
     return load_library().lattice_strerror(code).decode()
 
@@ -319,4 +460,5 @@ def velocity(spec: LatticeSpec, dt: float):
 
 
 __all__ = ["Lattice", "LatticeSpec", "LatticeError", "LatticeLibraryMissing",
-           "load_library", "strerror", "velocity", "EXPORTS"]
+           "Batch", "Member", "load_library", "strerror", "velocity",
+           "EXPORTS"]
