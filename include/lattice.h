@@ -277,6 +277,79 @@ int lattice_batch_sync(lattice_batch_t* B, int32_t* member_flags);
 
 int lattice_batch_destroy(lattice_batch_t* B);
 
+/* ===================================================================== *
+ * Coarse velocity lattice with a learned face-flux correction (2D, FP32).
+ *
+ * A coarse lattice keeps dx and dt and takes every 4th velocity of a fine
+ * one (vstride 4, nv_c = (nv_f - 1)/4 + 1, dv_c = 4 dv_f), so its streaming
+ * stays exact (Sec. 2).  With a network attached (lattice_mlp_attach), every
+ * lattice_step time step of a 2D nv = 17 FP32 lattice is followed by a
+ * correction: for each site and each interior velocity face of every line
+ * carrying at least line_eps of the site's mass, the network maps the
+ * face's 8 features [5-cell stencil from the upwind side / its mass m_s,
+ * |face drift| in cells per step, ln St, 0] to y; the face flux
+ * sign * m_s * y, limited to a quarter of the donor cell's mass, updates the
+ * state conservatively (f -= div G; mass exact, f >= 0 kept).
+ * Network: 8 -> 64 -> 64 -> 1, GELU (tanh form), bf16 weights and inputs on
+ * the matrix cores with FP32 accumulation.  Parameters are packed as
+ * W1[8][64], b1[64], W2[64][64], b2[64], w3[64], b3 (4801 floats).
+ * ===================================================================== */
+typedef struct lattice_mlp lattice_mlp_t;
+
+/* Mass-conservative restriction of a fine state (nv_fine = 4k + 1
+ * velocities per axis, [nv_f^dim][sites]) to the coarse lattice
+ * ([nv_c^dim][sites]): coarse cell J spans fine centres 4J-2..4J+2, the
+ * fine cells 4J+-2 being shared half/half.  Device pointers, asynchronous
+ * on stream.  EINVAL, EHIP. */
+int lattice_restrict(int32_t dim, int64_t sites, int32_t nv_fine,
+                     const float* f_fine, float* f_coarse, void* stream);
+
+/* Create a network (parameters zero) whose kernels run on stream. */
+int lattice_mlp_create(void* stream, lattice_mlp_t** out);
+/* Copy 4801 FP32 parameters from / to host memory (resets Adam). */
+int lattice_mlp_set_params(lattice_mlp_t* M, const float* host_params);
+int lattice_mlp_get_params(lattice_mlp_t* M, float* host_params);
+
+/* Training samples at nsites listed sites (device int32) of the coarse
+ * lattice L (2D, nv 17, FP32): with f_pred = one plain coarse step of the
+ * restricted fine state and f_true = the restricted fine state one step
+ * later (both device [289][ny][nx]), the residual r = f_true - f_pred is
+ * written as the face fluxes of least norm with -div G = r, and for every
+ * interior face (x-faces (row, k) then y-faces (k, column); 544 per site)
+ * X[8] = features of f_pred, t = sign * G / m_s, w = m_s.  Device outputs.
+ * Asynchronous.  EINVAL, ENOTSUP, EHIP. */
+int lattice_mlp_samples(lattice_t* L, double dt, double tau_p, double St,
+                        const float* f_pred, const float* f_true,
+                        const float* u, const int32_t* sites, int64_t nsites,
+                        float* X, float* t, float* w);
+
+/* Gradient of L = sum w (y - t)^2 / sum w over n samples (device X[n][8],
+ * t, w) into grad (device, 4801 floats, may be NULL) and *loss (host);
+ * weights and layer inputs rounded to bf16 as in the forward pass.
+ * Synchronous.  EINVAL, EHIP. */
+int lattice_mlp_grad(lattice_mlp_t* M, const float* X, const float* t,
+                     const float* w, int64_t n, float* grad, double* loss);
+
+/* steps Adam steps (lr, beta 0.9/0.999, eps 1e-8) on consecutive
+ * minibatches of batch samples (the data should be shuffled); *final_loss =
+ * loss of the last minibatch.  Synchronous.  EINVAL, EHIP. */
+int lattice_mlp_train(lattice_mlp_t* M, const float* X, const float* t,
+                      const float* w, int64_t n, int64_t batch, int64_t steps,
+                      double lr, double* final_loss);
+
+/* Network outputs y[n] for inputs X[n][8] (device), matrix-core path.
+ * Asynchronous.  EINVAL, EHIP. */
+int lattice_mlp_forward(lattice_mlp_t* M, const float* X, int64_t n,
+                        float* y);
+
+/* Attach (M != NULL) or detach (M == NULL) the correction to a coarse 2D
+ * lattice (nv 17, FP32); St and line_eps enter as described above.
+ * EINVAL, ENOTSUP. */
+int lattice_mlp_attach(lattice_t* L, lattice_mlp_t* M, double St,
+                       double line_eps);
+
+int lattice_mlp_destroy(lattice_mlp_t* M);
+
 #ifdef __cplusplus
 }
 #endif

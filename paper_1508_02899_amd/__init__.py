@@ -6,5 +6,5 @@ C ABI in ``include/lattice.h``; ``lattice`` is the Python binding and
 ``inputs`` the seeded synthetic flows and initial conditions.
 """
 from .lattice import (Batch, Lattice, LatticeError,  # noqa: F401
-                      LatticeLibraryMissing, LatticeSpec, Member,
-                      load_library, strerror, velocity)
+                      LatticeLibraryMissing, LatticeSpec, Member, Mlp,
+                      load_library, restrict, strerror, velocity)

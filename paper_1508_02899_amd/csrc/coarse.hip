@@ -1,0 +1,653 @@
+// coarse.hip -- coarse velocity lattice with a learned face-flux correction
+// (gfx950): fine -> coarse restriction, minimum-norm flux targets for
+// training, the network's training kernels (FP32) and its matrix-core
+// (bf16 MFMA, FP32 accumulation) inference fused with the conservative
+// correction of the coarse state.
+//
+// The coarse lattice keeps dx and dt and takes every 4th fine velocity
+// (velocity stride 4), so its streaming stays an exact integer shift
+// (Sec. 2: dx = dv dt).  After each coarse step (stream, drift, diffusion),
+// every interior velocity face of every site gets a correction flux
+//   G = sign * m_s * y,
+// y being the network's output for the face's 8 features (the 5-cell
+// stencil of the face, ordered from its upwind side and divided by the
+// stencil mass m_s; |face drift| in cells per step; ln St; 0), limited to
+// a quarter of the donor cell's mass (so no cell can go negative), and the
+// state is updated by f -= div G (mass is conserved exactly).
+#include <math.h>
+
+#include "coarse_internal.h"
+#include "lattice_internal.h"
+
+namespace lat {
+namespace {
+
+// ---------------------------------------------------------------- helpers
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t b) {
+  return __uint_as_float((uint32_t)b << 16);
+}
+__device__ __forceinline__ float qbf(float f) { return bf2f(f2bf(f)); }
+
+// GELU, tanh form (Hendrycks & Gimpel 2016), and its derivative.
+__device__ __forceinline__ float gelu(float z) {
+  const float a = 0.7978845608028654f, c = 0.044715f;
+  const float inner = a * z * (1.0f + c * z * z);
+  const float t = 1.0f - 2.0f / (1.0f + __expf(2.0f * inner));
+  return 0.5f * z * (1.0f + t);
+}
+__device__ __forceinline__ float gelu_d(float z, float* dg) {
+  const float a = 0.7978845608028654f, c = 0.044715f;
+  const float z2 = z * z;
+  const float inner = a * z * (1.0f + c * z2);
+  const float t = 1.0f - 2.0f / (1.0f + __expf(2.0f * inner));
+  *dg = 0.5f * (1.0f + t) + 0.5f * z * (1.0f - t * t) * a * (1.0f + 3.0f * c * z2);
+  return 0.5f * z * (1.0f + t);
+}
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ bf16x4 pack4(float a, float b, float c, float d) {
+  bf16x4 r;
+  r[0] = (short)f2bf(a);
+  r[1] = (short)f2bf(b);
+  r[2] = (short)f2bf(c);
+  r[3] = (short)f2bf(d);
+  return r;
+}
+
+// The network in matrix-core form.  16 inputs (faces) per wavefront pass;
+// each layer is computed transposed, D = W^T X^T, so that the 16x16x16
+// MFMA result layout (lane l: rows 4(l/16)+i, column l%16) is exactly the
+// B-operand layout of the next layer (lane l: k = 4(l/16)+i, column l%16).
+struct MlpRegs {
+  bf16x4 a1[4];      // W1^T tiles (units 16u.., features)
+  bf16x4 a2[4][4];   // W2^T tiles [unit tile][k step]
+  bf16x4 a3[4];      // w3 as row 0 of a 16-row A operand, per k step
+  float b1[4][4], b2[4][4];  // biases of this lane's D rows
+  float b3;
+};
+
+__device__ void load_mlp(MlpRegs& R, const float* __restrict__ P,
+                         const uint16_t* __restrict__ wq) {
+  const int l = (int)threadIdx.x & 63;
+  const int col = l & 15, ks = l >> 4;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int k = 4 * ks + i, unit = 16 * u + col;
+      R.a1[u][i] = k < kNF ? (short)wq[kOffW1 + k * kNH + unit] : (short)0;
+    }
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int k = 16 * kk + 4 * ks + i, unit = 16 * u + col;
+        R.a2[u][kk][i] = (short)wq[kOffW2 + k * kNH + unit];
+      }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      R.b1[u][i] = P[kOffB1 + 16 * u + 4 * ks + i];
+      R.b2[u][i] = P[kOffB2 + 16 * u + 4 * ks + i];
+    }
+  }
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      R.a3[kk][i] = col == 0 ? (short)wq[kOffW3 + 16 * kk + 4 * ks + i]
+                             : (short)0;
+  R.b3 = P[kOffB3];
+}
+
+// x = this lane's 4 features (k = 4(l/16)+i of input column l%16; zero for
+// l >= 32).  Returns the output of column l%16 in lanes 0..15.
+__device__ __forceinline__ float mlp_forward(const MlpRegs& R, bf16x4 x) {
+  const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+  bf16x4 h1[4], h2[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const f32x4 d = mfma16(R.a1[u], x, z);
+    h1[u] = pack4(gelu(d[0] + R.b1[u][0]), gelu(d[1] + R.b1[u][1]),
+                  gelu(d[2] + R.b1[u][2]), gelu(d[3] + R.b1[u][3]));
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    f32x4 d = z;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) d = mfma16(R.a2[u][kk], h1[kk], d);
+    h2[u] = pack4(gelu(d[0] + R.b2[u][0]), gelu(d[1] + R.b2[u][1]),
+                  gelu(d[2] + R.b2[u][2]), gelu(d[3] + R.b2[u][3]));
+  }
+  f32x4 y = z;
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) y = mfma16(R.a3[kk], h2[kk], y);
+  return y[0] + R.b3;
+}
+
+// -------------------------------------------------------------- restriction
+// Coarse cell J spans fine centres 4J-2..4J+2: fine cells 4J-1..4J+1 count
+// fully, 4J+-2 half (tensor product in 2D); densities scale by 1/4 per axis.
+__global__ __launch_bounds__(256) void k_restrict2d(const float* __restrict__ ff,
+                                                    float* __restrict__ fc,
+                                                    int64_t sites, int nvf) {
+  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (s >= sites) return;
+  const int nvc = (nvf - 1) / 4 + 1;
+  const int J = blockIdx.y, Jy = J / nvc, Jx = J - Jy * nvc;
+  float acc = 0.f;
+  for (int oy = -2; oy <= 2; ++oy) {
+    const int jy = 4 * Jy + oy;
+    if (jy < 0 || jy >= nvf) continue;
+    const float wy = (oy == -2 || oy == 2) ? 0.5f : 1.f;
+    for (int ox = -2; ox <= 2; ++ox) {
+      const int jx = 4 * Jx + ox;
+      if (jx < 0 || jx >= nvf) continue;
+      const float wx = (ox == -2 || ox == 2) ? 0.5f : 1.f;
+      acc += wy * wx * ff[(size_t)(jy * nvf + jx) * sites + s];
+    }
+  }
+  fc[(size_t)J * sites + s] = acc * (1.f / 16.f);
+}
+
+__global__ __launch_bounds__(256) void k_restrict1d(const float* __restrict__ ff,
+                                                    float* __restrict__ fc,
+                                                    int64_t sites, int nvf) {
+  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (s >= sites) return;
+  const int J = blockIdx.y;
+  float acc = 0.f;
+  for (int o = -2; o <= 2; ++o) {
+    const int j = 4 * J + o;
+    if (j < 0 || j >= nvf) continue;
+    acc += ((o == -2 || o == 2) ? 0.5f : 1.f) * ff[(size_t)j * sites + s];
+  }
+  fc[(size_t)J * sites + s] = acc * 0.25f;
+}
+
+// ---------------------------------------------------------- face features
+// Features of interior face k (cells k-1 | k) of one velocity line of a
+// site; line(i) returns the density of cell i (0 outside the line).
+template <typename LINE>
+__device__ __forceinline__ void face_feat(LINE line, int nv, int k, float u,
+                                          const CoarseGeom& g, float* st,
+                                          float* ms, float* sg, float* anu) {
+  const int h = (nv - 1) / 2;
+  const float vface = ((float)k - 0.5f - (float)h) * g.dv;
+  const float nu = g.nu_scale * (u - vface);
+  const bool up = nu >= 0.f;
+  float m = 0.f;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    const int c = up ? k - 3 + i : k + 2 - i;
+    const float v = (c >= 0 && c < nv) ? line(c) : 0.f;
+    st[i] = v;
+    m += v;
+  }
+  *ms = m;
+  *sg = up ? 1.f : -1.f;
+  *anu = up ? nu : -nu;
+}
+
+// ---------------------------------------------------------- flux targets
+// One workgroup per listed site.  r = f_true - f_pred; the face fluxes with
+// -div G = r of least norm are G = D^T psi with (D D^T) psi = -r, D D^T
+// being the Neumann Laplacian of the velocity square, diagonal in the
+// cosine (DCT-II) basis with eigenvalues lam_kx + lam_ky,
+// lam_k = 4 sin^2(pi k / (2 nv)).
+template <int NV>
+__global__ __launch_bounds__(320) void k_flux_samples(
+    CoarseGeom g, const float* __restrict__ fp, const float* __restrict__ ft,
+    const float* __restrict__ u, const int32_t* __restrict__ sites,
+    float* __restrict__ X, float* __restrict__ T, float* __restrict__ Wt) {
+  constexpr int N2 = NV * NV;
+  constexpr int NFACE = 2 * NV * (NV - 1);
+  __shared__ float cs[NV][NV];
+  __shared__ float lam[NV];
+  __shared__ float r[N2], a[N2], pred[N2];
+  const int tid = (int)threadIdx.x, bd = (int)blockDim.x;
+  const int64_t S = (int64_t)g.nx * g.ny;
+  const int site = sites[blockIdx.x];
+  for (int i = tid; i < N2; i += bd) {
+    const int k = i / NV, j = i - k * NV;
+    const float ck = k == 0 ? sqrtf(1.0f / NV) : sqrtf(2.0f / NV);
+    cs[k][j] = ck * cospif((float)k * ((float)j + 0.5f) / (float)NV);
+    const float p = fp[(size_t)i * S + site];
+    pred[i] = p;
+    r[i] = ft[(size_t)i * S + site] - p;
+  }
+  for (int k = tid; k < NV; k += bd) {
+    const float sk = sinpif((float)k / (2.0f * NV));
+    lam[k] = 4.0f * sk * sk;
+  }
+  __syncthreads();
+  // forward transform along x, then y
+  for (int i = tid; i < N2; i += bd) {
+    const int jy = i / NV, kx = i - jy * NV;
+    float s = 0.f;
+    for (int jx = 0; jx < NV; ++jx) s += cs[kx][jx] * r[jy * NV + jx];
+    a[i] = s;
+  }
+  __syncthreads();
+  for (int i = tid; i < N2; i += bd) {
+    const int ky = i / NV, kx = i - ky * NV;
+    float s = 0.f;
+    for (int jy = 0; jy < NV; ++jy) s += cs[ky][jy] * a[jy * NV + kx];
+    const float den = lam[kx] + lam[ky];
+    r[i] = (i == 0) ? 0.f : -s / den;  // psi in the cosine basis
+  }
+  __syncthreads();
+  // inverse transform along y, then x
+  for (int i = tid; i < N2; i += bd) {
+    const int jy = i / NV, kx = i - jy * NV;
+    float s = 0.f;
+    for (int ky = 0; ky < NV; ++ky) s += cs[ky][jy] * r[ky * NV + kx];
+    a[i] = s;
+  }
+  __syncthreads();
+  for (int i = tid; i < N2; i += bd) {
+    const int jy = i / NV, jx = i - jy * NV;
+    float s = 0.f;
+    for (int kx = 0; kx < NV; ++kx) s += cs[kx][jx] * a[jy * NV + kx];
+    r[i] = s;  // psi
+  }
+  __syncthreads();
+  const float ux = u[site], uy = u[S + site];
+  const size_t base = (size_t)blockIdx.x * NFACE;
+  for (int f = tid; f < NFACE; f += bd) {
+    float st[5], ms, sg, anu, G;
+    if (f < NV * (NV - 1)) {  // x-face (row jy, face k)
+      const int jy = f / (NV - 1), k = f - jy * (NV - 1) + 1;
+      auto line = [&](int c) { return pred[jy * NV + c]; };
+      face_feat(line, NV, k, ux, g, st, &ms, &sg, &anu);
+      G = r[jy * NV + k - 1] - r[jy * NV + k];
+    } else {  // y-face (face k, column jx)
+      const int q = f - NV * (NV - 1);
+      const int k = q / NV + 1, jx = q - (k - 1) * NV;
+      auto line = [&](int c) { return pred[c * NV + jx]; };
+      face_feat(line, NV, k, uy, g, st, &ms, &sg, &anu);
+      G = r[(k - 1) * NV + jx] - r[k * NV + jx];
+    }
+    const float inv = ms > 0.f ? 1.0f / ms : 0.f;
+    float* x = X + (base + f) * kNF;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) x[i] = st[i] * inv;
+    x[5] = anu;
+    x[6] = g.log_st;
+    x[7] = 0.f;
+    T[base + f] = sg * G * inv;
+    Wt[base + f] = ms;
+  }
+}
+
+// --------------------------------------------------------------- training
+// Gradients of L = sum_i w_i (y_i - t_i)^2 / sum_i w_i, weights and layer
+// inputs rounded to bf16 as in the matrix-core forward (the rounding passed
+// straight through).  One wavefront per block walks its share of samples
+// 64 at a time: per-sample activations in LDS, then every lane accumulates
+// its own parameters (p = lane + 64 m) over the 64 samples.
+constexpr int kOwn = (kNParams + 63) / 64;  // 76 parameters per lane
+
+__global__ __launch_bounds__(64) void k_mlp_grad(
+    const float* __restrict__ P, const float* __restrict__ X,
+    const float* __restrict__ T, const float* __restrict__ Wt, int64_t n,
+    float inv_wsum, float* __restrict__ partial, int nblocks) {
+  __shared__ float w1[kNF * kNH], b1[kNH], w2[kNH * kNH], b2[kNH], w3[kNH];
+  __shared__ float sx[64][kNF + 1];
+  __shared__ float sh1[64][kNH + 1], sh2[64][kNH + 1];
+  __shared__ float sd1[64][kNH + 1], sd2[64][kNH + 1];
+  __shared__ float sdy[64];
+  __shared__ float sl[64];
+  __shared__ float sacc[kOwn][64];  // this block's gradient, lane-owned
+  const int tid = (int)threadIdx.x;
+  for (int m = 0; m < kOwn; ++m) sacc[m][tid] = 0.f;
+  for (int i = tid; i < kNF * kNH; i += 64) w1[i] = qbf(P[kOffW1 + i]);
+  for (int i = tid; i < kNH * kNH; i += 64) w2[i] = qbf(P[kOffW2 + i]);
+  for (int i = tid; i < kNH; i += 64) {
+    b1[i] = P[kOffB1 + i];
+    b2[i] = P[kOffB2 + i];
+    w3[i] = qbf(P[kOffW3 + i]);
+  }
+  const float b3 = P[kOffB3];
+  __syncthreads();
+  float lsum = 0.f;
+  const int64_t lo = n * blockIdx.x / nblocks, hi = n * (blockIdx.x + 1) / nblocks;
+  for (int64_t base = lo; base < hi; base += 64) {
+    const int64_t i = base + tid;
+    const bool valid = i < hi;
+    float x[kNF];
+#pragma unroll
+    for (int k = 0; k < kNF; ++k) x[k] = valid ? qbf(X[i * kNF + k]) : 0.f;
+    const float t = valid ? T[i] : 0.f, w = valid ? Wt[i] : 0.f;
+    // forward
+    float z2[kNH];
+#pragma unroll
+    for (int j = 0; j < kNH; ++j) z2[j] = b2[j];
+    for (int j = 0; j < kNH; ++j) {
+      float z = b1[j];
+#pragma unroll
+      for (int k = 0; k < kNF; ++k) z += x[k] * w1[k * kNH + j];
+      float dg;
+      const float h = qbf(gelu_d(z, &dg));
+      sh1[tid][j] = h;
+      sd1[tid][j] = dg;  // gelu'(z1), replaced by dz1 below
+#pragma unroll
+      for (int q = 0; q < kNH; ++q) z2[q] += h * w2[j * kNH + q];
+    }
+    float y = b3;
+    float dz2[kNH];
+#pragma unroll
+    for (int j = 0; j < kNH; ++j) {
+      float dg;
+      const float h = qbf(gelu_d(z2[j], &dg));
+      sh2[tid][j] = h;
+      y += h * w3[j];
+      dz2[j] = dg;
+    }
+    const float e = y - t;
+    lsum += w * e * e * inv_wsum;
+    const float dy = 2.0f * w * e * inv_wsum;
+    sdy[tid] = dy;
+#pragma unroll
+    for (int j = 0; j < kNH; ++j) {
+      dz2[j] *= dy * w3[j];
+      sd2[tid][j] = dz2[j];
+    }
+    for (int j = 0; j < kNH; ++j) {
+      float dh = 0.f;
+#pragma unroll
+      for (int q = 0; q < kNH; ++q) dh += dz2[q] * w2[j * kNH + q];
+      sd1[tid][j] = dh * sd1[tid][j];
+    }
+#pragma unroll
+    for (int k = 0; k < kNF; ++k) sx[tid][k] = x[k];
+    __syncthreads();
+    // accumulate this lane's parameters over the 64 samples
+    for (int m = 0; m < kOwn; ++m) {
+      const int p = tid + 64 * m;
+      float s = 0.f;
+      if (p < kOffB1) {  // W1[k][j]
+        const int k = p / kNH, j = p - k * kNH;
+        for (int b = 0; b < 64; ++b) s += sx[b][k] * sd1[b][j];
+      } else if (p < kOffW2) {  // b1[j]
+        const int j = p - kOffB1;
+        for (int b = 0; b < 64; ++b) s += sd1[b][j];
+      } else if (p < kOffB2) {  // W2[i][j]
+        const int q = p - kOffW2, ii = q / kNH, j = q - ii * kNH;
+        for (int b = 0; b < 64; ++b) s += sh1[b][ii] * sd2[b][j];
+      } else if (p < kOffW3) {  // b2[j]
+        const int j = p - kOffB2;
+        for (int b = 0; b < 64; ++b) s += sd2[b][j];
+      } else if (p < kOffB3) {  // w3[j]
+        const int j = p - kOffW3;
+        for (int b = 0; b < 64; ++b) s += sh2[b][j] * sdy[b];
+      } else if (p == kOffB3) {
+        for (int b = 0; b < 64; ++b) s += sdy[b];
+      }
+      sacc[m][tid] += s;
+    }
+    __syncthreads();
+  }
+  float* out = partial + (size_t)blockIdx.x * (kNParams + 1);
+  for (int m = 0; m < kOwn; ++m) {
+    const int p = tid + 64 * m;
+    if (p < kNParams) out[p] = sacc[m][tid];
+  }
+  sl[tid] = lsum;
+  __syncthreads();
+  if (tid == 0) {
+    float s = 0.f;
+    for (int b = 0; b < 64; ++b) s += sl[b];
+    out[kNParams] = s;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_grad_reduce(const float* __restrict__ partial,
+                                                     int nblocks,
+                                                     float* __restrict__ grad,
+                                                     float* __restrict__ loss) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p > kNParams) return;
+  float s = 0.f;
+  for (int b = 0; b < nblocks; ++b) s += partial[(size_t)b * (kNParams + 1) + p];
+  if (p < kNParams)
+    grad[p] = s;
+  else
+    loss[0] = s;
+}
+
+// Adam (Kingma & Ba 2015).
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ P,
+                                              float* __restrict__ m,
+                                              float* __restrict__ v,
+                                              const float* __restrict__ g,
+                                              int step, float lr, float b1,
+                                              float b2, float eps) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= kNParams) return;
+  const float gi = g[p];
+  const float mi = b1 * m[p] + (1.f - b1) * gi;
+  const float vi = b2 * v[p] + (1.f - b2) * gi * gi;
+  m[p] = mi;
+  v[p] = vi;
+  const float mh = mi / (1.f - powf(b1, (float)step));
+  const float vh = vi / (1.f - powf(b2, (float)step));
+  P[p] -= lr * mh / (sqrtf(vh) + eps);
+}
+
+__global__ __launch_bounds__(256) void k_pack_bf16(const float* __restrict__ P,
+                                                   uint16_t* __restrict__ wq) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p < kNParams) wq[p] = f2bf(P[p]);
+}
+
+// ------------------------------------------------------ network forward
+__global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ P,
+                                                     const uint16_t* __restrict__ wq,
+                                                     const float* __restrict__ X,
+                                                     int64_t n,
+                                                     float* __restrict__ Y) {
+  MlpRegs R;
+  load_mlp(R, P, wq);
+  const int l = (int)threadIdx.x & 63;
+  const int64_t chunk = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6));
+  const int64_t i = chunk * 16 + (l & 15);
+  const int ks = l >> 4;
+  float f[4] = {0.f, 0.f, 0.f, 0.f};
+  if (ks < 2 && i < n)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) f[q] = X[i * kNF + 4 * ks + q];
+  const float y = mlp_forward(R, pack4(f[0], f[1], f[2], f[3]));
+  if (l < 16 && i < n) Y[i] = y;
+}
+
+// ---------------------------------------------------- fused correction
+// 17^2 coarse velocities.  A workgroup loads a tile of TS sites (coalesced,
+// all 289 planes) into LDS; each wavefront corrects its sites one at a
+// time: every velocity line with at least line_eps of the site's mass gets
+// its 16 interior face fluxes from one matrix-core pass; the limited fluxes
+// update the site's cells; the tile is stored back.
+constexpr int kNVC = 17;
+constexpr int kTS = 32;
+
+__global__ __launch_bounds__(256) void k_mlp_correct17(
+    CoarseGeom g, const float* __restrict__ P, const uint16_t* __restrict__ wq,
+    float* __restrict__ f, const float* __restrict__ u,
+    const int* __restrict__ flag) {
+  constexpr int NV = kNVC, N2 = NV * NV;
+  __shared__ float tile[N2][kTS + 1];
+  __shared__ float gx[4][NV][NV + 1];  // x-face fluxes [row][face 0..NV]
+  __shared__ float gy[4][NV + 1][NV];  // y-face fluxes [face 0..NV][col]
+  __shared__ float lm[4][2 * NV];      // line masses
+  if (*flag != 0) return;
+  MlpRegs R;
+  load_mlp(R, P, wq);
+  const int tid = (int)threadIdx.x, l = tid & 63, w = tid >> 6;
+  const int64_t S = (int64_t)g.nx * g.ny;
+  const int64_t s0 = (int64_t)blockIdx.x * kTS;
+  const int nts = (int)((S - s0) < kTS ? (S - s0) : kTS);
+  for (int i = tid; i < N2 * kTS; i += 256) {
+    const int J = i / kTS, s = i - J * kTS;
+    tile[J][s] = s < nts ? f[(size_t)J * S + s0 + s] : 0.f;
+  }
+  __syncthreads();
+  const int col = l & 15, ks = l >> 4;
+  for (int s = w; s < nts; s += 4) {
+    const int64_t site = s0 + s;
+    const float ux = u[site], uy = u[S + site];
+    // line masses: rows (lanes 0..16), columns (lanes 32..48)
+    if (l < NV) {
+      float m = 0.f;
+      for (int j = 0; j < NV; ++j) m += tile[l * NV + j][s];
+      lm[w][l] = m;
+    } else if (l >= 32 && l < 32 + NV) {
+      float m = 0.f;
+      for (int j = 0; j < NV; ++j) m += tile[j * NV + (l - 32)][s];
+      lm[w][NV + l - 32] = m;
+    }
+    for (int i = l; i < NV * (NV + 1); i += 64) {
+      (&gx[w][0][0])[i] = 0.f;
+      (&gy[w][0][0])[i] = 0.f;
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    float M = 0.f;
+    for (int j = 0; j < NV; ++j) M += lm[w][j];
+    const float thr = g.line_eps * M;
+    for (int line = 0; line < 2 * NV; ++line) {
+      if (!(lm[w][line] >= thr) || !(lm[w][line] > 0.f)) continue;  // uniform
+      const int axis = line >= NV, a = line - axis * NV;
+      const int k = col + 1;  // face of this lane's column
+      float st[5], ms, sg, anu;
+      if (axis == 0) {
+        auto ln = [&](int c) { return tile[a * NV + c][s]; };
+        face_feat(ln, NV, k, ux, g, st, &ms, &sg, &anu);
+      } else {
+        auto ln = [&](int c) { return tile[c * NV + a][s]; };
+        face_feat(ln, NV, k, uy, g, st, &ms, &sg, &anu);
+      }
+      const float inv = ms > 0.f ? 1.0f / ms : 0.f;
+      bf16x4 x;
+      if (ks == 0)
+        x = pack4(st[0] * inv, st[1] * inv, st[2] * inv, st[3] * inv);
+      else if (ks == 1)
+        x = pack4(st[4] * inv, anu, g.log_st, 0.f);
+      else
+        x = pack4(0.f, 0.f, 0.f, 0.f);
+      const float y = mlp_forward(R, x);
+      if (l < 16) {
+        float G = sg * ms * y;
+        const float donor = axis == 0 ? tile[a * NV + (G > 0.f ? k - 1 : k)][s]
+                                      : tile[(G > 0.f ? k - 1 : k) * NV + a][s];
+        const float cap = 0.25f * donor;
+        G = G > cap ? cap : (G < -cap ? -cap : G);
+        if (axis == 0)
+          gx[w][a][k] = G;
+        else
+          gy[w][k][a] = G;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    for (int J = l; J < N2; J += 64) {
+      const int jy = J / NV, jx = J - jy * NV;
+      tile[J][s] -= (gx[w][jy][jx + 1] - gx[w][jy][jx]) +
+                    (gy[w][jy + 1][jx] - gy[w][jy][jx]);
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  }
+  __syncthreads();
+  for (int i = tid; i < N2 * kTS; i += 256) {
+    const int J = i / kTS, s = i - J * kTS;
+    if (s < nts) f[(size_t)J * S + s0 + s] = tile[J][s];
+  }
+}
+
+}  // namespace
+
+hipError_t launch_restrict(int dim, int64_t sites, int nv_fine,
+                           const float* ff, float* fc, hipStream_t s) {
+  if ((nv_fine - 1) % 4 || nv_fine < 5) return hipErrorInvalidValue;
+  const int nvc = (nv_fine - 1) / 4 + 1;
+  const int gx = (int)((sites + 255) / 256);
+  if (dim == 1)
+    hipLaunchKernelGGL(k_restrict1d, dim3(gx, nvc), dim3(256), 0, s, ff, fc,
+                       sites, nv_fine);
+  else
+    hipLaunchKernelGGL(k_restrict2d, dim3(gx, nvc * nvc), dim3(256), 0, s, ff,
+                       fc, sites, nv_fine);
+  return hipGetLastError();
+}
+
+hipError_t launch_flux_samples(const CoarseGeom& g, const float* f_pred,
+                               const float* f_true, const float* u,
+                               const int32_t* sites, int nsites, float* X,
+                               float* t, float* w, hipStream_t s) {
+  if (g.nv != kNVC || nsites < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_flux_samples<kNVC>, dim3(nsites), dim3(320), 0, s, g,
+                     f_pred, f_true, u, sites, X, t, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_grad(const float* params, const float* X,
+                           const float* t, const float* w, int64_t n,
+                           double wsum, float* partial, int nblocks,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_mlp_grad, dim3(nblocks), dim3(64), 0, s, params, X, t,
+                     w, n, (float)(1.0 / wsum), partial, nblocks);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_reduce(const float* partial, int nblocks, float* grad,
+                              float* loss, hipStream_t s) {
+  hipLaunchKernelGGL(k_grad_reduce, dim3((kNParams + 1 + 255) / 256),
+                     dim3(256), 0, s, partial, nblocks, grad, loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float* params, float* m, float* v, const float* grad,
+                       int step, float lr, float b1, float b2, float eps,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_adam, dim3((kNParams + 255) / 256), dim3(256), 0, s,
+                     params, m, v, grad, step, lr, b1, b2, eps);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_bf16(const float* params, uint16_t* wq, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_bf16, dim3((kNParams + 255) / 256), dim3(256), 0,
+                     s, params, wq);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_correct(const CoarseGeom& g, const float* params,
+                              const uint16_t* wq, float* f, const float* u,
+                              const int* flag, hipStream_t s) {
+  if (g.nv != kNVC) return hipErrorInvalidValue;
+  const int64_t S = (int64_t)g.nx * g.ny;
+  const int grid = (int)((S + kTS - 1) / kTS);
+  hipLaunchKernelGGL(k_mlp_correct17, dim3(grid), dim3(256), 0, s, g, params,
+                     wq, f, u, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(const float* params, const uint16_t* wq,
+                              const float* X, int64_t n, float* y,
+                              hipStream_t s) {
+  const int64_t chunks = (n + 15) / 16;
+  const int grid = (int)((chunks + 3) / 4);
+  hipLaunchKernelGGL(k_mlp_forward, dim3(grid), dim3(256), 0, s, params, wq, X,
+                     n, y);
+  return hipGetLastError();
+}
+
+}  // namespace lat

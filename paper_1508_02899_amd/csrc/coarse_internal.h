@@ -1,0 +1,69 @@
+// coarse_internal.h -- launch interface of the coarse-velocity-lattice form
+// with the learned face-flux correction (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lat {
+
+// Parameter packing of the correction network (FP32 master copy):
+//   W1[8][64], b1[64], W2[64][64], b2[64], w3[64], b3
+constexpr int kNF = 8;    // input features (7 used + 1 zero pad)
+constexpr int kNH = 64;   // hidden width
+constexpr int kOffW1 = 0;
+constexpr int kOffB1 = kOffW1 + kNF * kNH;
+constexpr int kOffW2 = kOffB1 + kNH;
+constexpr int kOffB2 = kOffW2 + kNH * kNH;
+constexpr int kOffW3 = kOffB2 + kNH;
+constexpr int kOffB3 = kOffW3 + kNH;
+constexpr int kNParams = kOffB3 + 1;  // 4801
+
+// Geometry of a coarse 2D lattice seen by the correction / sampling kernels.
+struct CoarseGeom {
+  int nx, ny, nv;
+  float dv;       // coarse velocity spacing
+  float nu_scale; // dt / (tau_p dv): face drift per unit of (u - v_face)
+  float log_st;   // ln St
+  float line_eps; // lines with less than line_eps x site mass are skipped
+};
+
+hipError_t launch_restrict(int dim, int64_t sites, int nv_fine,
+                           const float* ff, float* fc, hipStream_t s);
+
+// Training samples of the face-flux correction at the listed sites:
+// residual r = f_true - f_pred, minimum-norm face fluxes G with
+// -div G = r, features of every interior face from f_pred and u.
+// Outputs per site (2 nv (nv-1) faces): X[face][8], t[face], w[face].
+hipError_t launch_flux_samples(const CoarseGeom& g, const float* f_pred,
+                               const float* f_true, const float* u,
+                               const int32_t* sites, int nsites, float* X,
+                               float* t, float* w, hipStream_t s);
+
+// Per-block partial gradients of the weighted squared loss over n samples
+// (nblocks rows of kNParams + 1 floats: gradient, then the block's loss sum).
+hipError_t launch_mlp_grad(const float* params, const float* X,
+                           const float* t, const float* w, int64_t n,
+                           double wsum, float* partial, int nblocks,
+                           hipStream_t s);
+// Sum of the partials in block order into grad[kNParams] and loss[0].
+hipError_t launch_grad_reduce(const float* partial, int nblocks, float* grad,
+                              float* loss, hipStream_t s);
+hipError_t launch_adam(float* params, float* m, float* v, const float* grad,
+                       int step, float lr, float b1, float b2, float eps,
+                       hipStream_t s);
+// bf16 copies of the weights for the matrix-core forward pass.
+hipError_t launch_pack_bf16(const float* params, uint16_t* wq, hipStream_t s);
+
+// In-place learned correction of a coarse 2D state f[nv*nv][ny][nx]
+// (nv = 17): per site, per velocity line, the network's face fluxes,
+// limited to a quarter of the donor cell, applied conservatively.
+hipError_t launch_mlp_correct(const CoarseGeom& g, const float* params,
+                              const uint16_t* wq, float* f, const float* u,
+                              const int* flag, hipStream_t s);
+// Forward pass only (network outputs for X[n][8]) -- for checks.
+hipError_t launch_mlp_forward(const float* params, const uint16_t* wq,
+                              const float* X, int64_t n, float* y,
+                              hipStream_t s);
+
+}  // namespace lat

@@ -13,27 +13,8 @@
 
 #include "../../include/lattice.h"
 #include "lattice_internal.h"
+#include "lattice_struct.h"
 
-struct lattice {
-  lattice_desc d;
-  int64_t sites;    // nx * ny
-  int64_t nplanes;  // nv^dim
-  int64_t cells;    // sites * nplanes
-  size_t elem;      // sizeof state element
-  hipStream_t stream;
-  void* scratch = nullptr;      // state-sized ping-pong twin
-  int* flag = nullptr;          // sticky CFL / finiteness flag (device)
-  double* plane_sums = nullptr; // nplanes doubles
-  double* red = nullptr;        // 8 doubles: moments / absmax
-  double* host_red = nullptr;   // pinned mirror of red
-  char msg[512];
-  // profiling
-  bool prof = false;
-  std::vector<hipEvent_t> ev;   // pairs (start, stop)
-  size_t ev_used = 0;
-  double prof_ms = 0.0;
-  int64_t prof_launches = 0;
-};
 
 namespace {
 
@@ -271,6 +252,8 @@ int lattice_step(lattice_t* L, void* f, const void* u, int64_t n_u_slices,
       if (e != hipSuccess) return hip_err(L, e, "step kernel launch");
       HIPCHK(L, record_pair(L, true));
     }
+    if (L->mlp)  // learned face-flux correction of the coarse lattice
+      HIPCHK(L, lat::apply_mlp(L, bufs[k & 1], a.u, dt, tau_p));
   }
   return LATTICE_OK;
 }

@@ -30,8 +30,13 @@ EXPORTS = (
     "lattice_profile_read", "lattice_destroy", "lattice_strerror",
     "lattice_last_error", "lattice_batch_init", "lattice_batch_layout",
     "lattice_batch_tune", "lattice_batch_step", "lattice_batch_moments",
-    "lattice_batch_sync", "lattice_batch_destroy",
+    "lattice_batch_sync", "lattice_batch_destroy", "lattice_restrict",
+    "lattice_mlp_create", "lattice_mlp_set_params", "lattice_mlp_get_params",
+    "lattice_mlp_samples", "lattice_mlp_grad", "lattice_mlp_train",
+    "lattice_mlp_forward", "lattice_mlp_attach", "lattice_mlp_destroy",
 )
+
+MLP_NPARAMS = 4801  # W1[8][64], b1[64], W2[64][64], b2[64], w3[64], b3
 
 
 class LatticeLibraryMissing(RuntimeError):
@@ -130,6 +135,21 @@ def load_library(path: str = LIB_PATH):
     L.lattice_batch_moments.argtypes = [vp, vp, ctypes.POINTER(dbl)]
     L.lattice_batch_sync.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     L.lattice_batch_destroy.argtypes = [vp]
+    pf = ctypes.POINTER(ctypes.c_float)
+    L.lattice_restrict.argtypes = [ctypes.c_int32, i64, ctypes.c_int32, vp, vp,
+                                   vp]
+    L.lattice_mlp_create.argtypes = [vp, ctypes.POINTER(vp)]
+    L.lattice_mlp_set_params.argtypes = [vp, pf]
+    L.lattice_mlp_get_params.argtypes = [vp, pf]
+    L.lattice_mlp_samples.argtypes = [vp, dbl, dbl, dbl, vp, vp, vp, vp, i64,
+                                      vp, vp, vp]
+    L.lattice_mlp_grad.argtypes = [vp, vp, vp, vp, i64, vp,
+                                   ctypes.POINTER(dbl)]
+    L.lattice_mlp_train.argtypes = [vp, vp, vp, vp, i64, i64, i64, dbl,
+                                    ctypes.POINTER(dbl)]
+    L.lattice_mlp_forward.argtypes = [vp, vp, i64, vp]
+    L.lattice_mlp_attach.argtypes = [vp, vp, dbl, dbl]
+    L.lattice_mlp_destroy.argtypes = [vp]
     for name in EXPORTS:
         getattr(L, name)  # every declared entry point must be exported
     _lib = L
@@ -440,6 +460,121 @@ class Batch:
             pass
 
 
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def restrict(f_fine, dim: int, stream=None):
+    """Mass-conservative fine -> coarse (stride 4) restriction on the GPU;
+    f_fine [nv_f^dim, ...] FP32 CUDA tensor; returns a new coarse tensor."""
+    torch = _torch()
+    L = load_library()
+    nvf = int(round(f_fine.shape[0] ** (1.0 / dim)))
+    nvc = (nvf - 1) // 4 + 1
+    sites = f_fine.numel() // f_fine.shape[0]
+    out = torch.empty((nvc ** dim,) + tuple(f_fine.shape[1:]),
+                      dtype=torch.float32, device=f_fine.device)
+    s = stream or torch.cuda.current_stream()
+    rc = L.lattice_restrict(dim, sites, nvf, _ptr(f_fine), _ptr(out),
+                            ctypes.c_void_p(s.cuda_stream))
+    if rc != OK:
+        raise LatticeError(rc, strerror(rc))
+    return out
+
+
+class Mlp:
+    """The face-flux correction network (``lattice_mlp_t``)."""
+
+    def __init__(self, stream=None):
+        torch = _torch()
+        self._M = None
+        self.lib = load_library()
+        self.stream = stream or torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        rc = self.lib.lattice_mlp_create(ctypes.c_void_p(self.stream.cuda_stream),
+                                         ctypes.byref(h))
+        if rc != OK:
+            raise LatticeError(rc, strerror(rc))
+        self._M = h
+
+    def _check(self, rc):
+        if rc != OK:
+            raise LatticeError(rc, strerror(rc))
+
+    def set_params(self, p):
+        import numpy as np
+        a = np.ascontiguousarray(np.asarray(p, dtype=np.float32).ravel())
+        assert a.size == MLP_NPARAMS
+        self._check(self.lib.lattice_mlp_set_params(
+            self._M, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+    def get_params(self):
+        import numpy as np
+        a = np.empty(MLP_NPARAMS, dtype=np.float32)
+        self._check(self.lib.lattice_mlp_get_params(
+            self._M, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return a
+
+    def grad(self, X, t, w):
+        torch = _torch()
+        g = torch.empty(MLP_NPARAMS, dtype=torch.float32, device=X.device)
+        loss = ctypes.c_double()
+        self._check(self.lib.lattice_mlp_grad(self._M, _ptr(X), _ptr(t), _ptr(w),
+                                              t.numel(), _ptr(g),
+                                              ctypes.byref(loss)))
+        return loss.value, g
+
+    def train(self, X, t, w, batch: int, steps: int, lr: float):
+        loss = ctypes.c_double()
+        self._check(self.lib.lattice_mlp_train(self._M, _ptr(X), _ptr(t),
+                                               _ptr(w), t.numel(), int(batch),
+                                               int(steps), float(lr),
+                                               ctypes.byref(loss)))
+        return loss.value
+
+    def forward(self, X):
+        torch = _torch()
+        n = X.shape[0]
+        y = torch.empty(n, dtype=torch.float32, device=X.device)
+        self._check(self.lib.lattice_mlp_forward(self._M, _ptr(X), n, _ptr(y)))
+        return y
+
+    def samples(self, lat, dt, tau_p, St, f_pred, f_true, u, sites):
+        """Training samples at the given sites (int32 CUDA tensor)."""
+        torch = _torch()
+        nf = 544
+        n = sites.numel() * nf
+        X = torch.empty((n, 8), dtype=torch.float32, device=f_pred.device)
+        t = torch.empty(n, dtype=torch.float32, device=f_pred.device)
+        w = torch.empty(n, dtype=torch.float32, device=f_pred.device)
+        self._check(self.lib.lattice_mlp_samples(
+            lat._L, float(dt), float(tau_p), float(St), _ptr(f_pred),
+            _ptr(f_true), _ptr(u), _ptr(sites), sites.numel(), _ptr(X),
+            _ptr(t), _ptr(w)))
+        return X, t, w
+
+    def attach(self, lat, St: float, line_eps: float = 1e-4):
+        self._check(self.lib.lattice_mlp_attach(lat._L, self._M, float(St),
+                                                float(line_eps)))
+
+    @staticmethod
+    def detach(lat):
+        rc = load_library().lattice_mlp_attach(lat._L, None, 1.0, 0.0)
+        if rc != OK:
+            raise LatticeError(rc, strerror(rc))
+
+    def close(self):
+        if self._M is not None:
+            self.lib.lattice_mlp_destroy(self._M)
+            self._M = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def strerror(code: int) -> str:
     return load_library().lattice_strerror(code).decode()
 
@@ -460,5 +595,5 @@ def velocity(spec: LatticeSpec, dt: float):
 
 
 __all__ = ["Lattice", "LatticeSpec", "LatticeError", "LatticeLibraryMissing",
-           "Batch", "Member", "load_library", "strerror", "velocity",
-           "EXPORTS"]
+           "Batch", "Member", "Mlp", "restrict", "load_library", "strerror",
+           "velocity", "EXPORTS", "MLP_NPARAMS"]

@@ -1,0 +1,117 @@
+"""Pins of the coarse-lattice / correction-network oracle (oracle/coarse.py)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import coarse as C
+
+
+def test_restrict_weights_partition_each_fine_cell():
+    R = C.restrict_weights(65)
+    assert R.shape == (17, 65)
+    np.testing.assert_array_equal(R.sum(axis=0), np.ones(65))
+    # coarse centre J sits on fine index 4J; symmetric weights
+    np.testing.assert_array_equal(R, R[::-1, ::-1])
+    assert R[3, 12] == 1 and R[3, 14] == 0.5 and R[4, 14] == 0.5
+
+
+def test_restrict_conserves_mass():
+    rng = np.random.default_rng(1)
+    nvf = 33
+    f = rng.random((nvf * nvf, 3, 4))
+    fc = C.restrict(f, 2)
+    # masses: fine cells weigh dv^2, coarse cells (4 dv)^2
+    assert fc.sum() * 16 == pytest.approx(f.sum(), rel=1e-14)
+
+
+def test_restrict_maps_coarse_centred_mass_exactly():
+    """Mass sitting on fine cells 4J (the coarse centres) lands unchanged in
+    coarse cell J (density divided by 4 per axis)."""
+    nvf = 17
+    f = np.zeros((nvf * nvf, 2))
+    f[(4 * 2) * nvf + 4 * 3, 0] = 8.0   # (jy, jx) = (8, 12) -> (2, 3)
+    f[(4 * 0) * nvf + 4 * 4, 1] = 16.0  # (0, 16) -> (0, 4)
+    fc = C.restrict(f, 2)
+    want = np.zeros((25, 2))
+    want[2 * 5 + 3, 0] = 0.5
+    want[0 * 5 + 4, 1] = 1.0
+    np.testing.assert_array_equal(fc, want)
+
+
+def test_minnorm_fluxes_reproduce_residual_and_lie_in_range():
+    rng = np.random.default_rng(2)
+    n = 7
+    r = rng.standard_normal((n * n, 5))
+    r -= r.mean(axis=0)
+    Gx, Gy = C.minnorm_fluxes(r, n)
+    G = np.concatenate([Gx.reshape(-1, 5), Gy.reshape(-1, 5)])
+    D = C.divergence_matrix(n)
+    np.testing.assert_allclose(-D @ G, r, atol=1e-12)
+    # least norm <=> G = D^T psi for some psi
+    psi, *_ = np.linalg.lstsq(D.T, G, rcond=None)
+    np.testing.assert_allclose(D.T @ psi, G, atol=1e-12)
+
+
+def test_divergence_matrix_is_conservative():
+    D = C.divergence_matrix(5)
+    np.testing.assert_array_equal(D.sum(axis=0), np.zeros(D.shape[1]))
+
+
+def test_mlp_gradient_matches_finite_differences():
+    rng = np.random.default_rng(3)
+    P = C.init_params(rng, scale=1.5)
+    P["b1"] = rng.standard_normal(C.NH) * 0.3
+    P["b2"] = rng.standard_normal(C.NH) * 0.3
+    X = rng.standard_normal((40, C.NF))
+    t = rng.standard_normal(40)
+    w = rng.random(40)
+    L, g = C.loss_and_grads(P, X, t, w, quantize=False)
+    h = 1e-6
+    for k, idx in [("W1", (3, 7)), ("b1", (11,)), ("W2", (5, 40)),
+                   ("b2", (63,)), ("w3", (17,)), ("b3", ())]:
+        Pp = {q: v.copy() for q, v in P.items()}
+        Pm = {q: v.copy() for q, v in P.items()}
+        Pp[k][idx] += h
+        Pm[k][idx] -= h
+        Lp, _ = C.loss_and_grads(Pp, X, t, w, quantize=False)
+        Lm, _ = C.loss_and_grads(Pm, X, t, w, quantize=False)
+        assert g[k][idx] == pytest.approx((Lp - Lm) / (2 * h), rel=1e-5, abs=1e-9)
+
+
+def test_gelu_closed_forms():
+    z = np.array([0.0, 1e-8, 30.0, -30.0])
+    g = C.gelu(z)
+    assert g[0] == 0.0 and g[2] == pytest.approx(30.0) and abs(g[3]) < 1e-12
+    assert C.gelu_grad(np.array([0.0]))[0] == pytest.approx(0.5)
+    # tanh form vs the exact erf form: |diff| < 1e-3 (published bound ~5e-4)
+    from scipy.special import erf
+    zz = np.linspace(-5, 5, 1001)
+    exact = 0.5 * zz * (1 + erf(zz / math.sqrt(2)))
+    assert np.abs(C.gelu(zz) - exact).max() < 1e-3
+
+
+def test_bf16_rounding():
+    assert C.bf16(1.0) == 1.0
+    assert C.bf16(1.0 + 2 ** -9) == 1.0          # ties to even
+    assert C.bf16(1.0 + 3 * 2 ** -9) == 1.0 + 2 ** -7
+    assert C.bf16(-3.0) == -3.0
+
+
+def test_adam_first_step_is_sign_step():
+    P = {"a": np.array([1.0, -2.0, 0.5])}
+    g = {"a": np.array([0.3, -4.0, 1e-3])}
+    st = {}
+    C.adam(P, g, st, lr=0.01)
+    np.testing.assert_allclose(P["a"], [0.99, -1.99, 0.49], atol=1e-7)
+
+
+def test_corrected_site_conserves_mass_and_positivity():
+    rng = np.random.default_rng(4)
+    nv = 9
+    fc = rng.random(nv * nv) ** 3
+    X, ms, sg = C.face_features(fc, nv, 0.4, -0.3, 0.5, 0.1, 1.0, 2.0)
+    y = rng.standard_normal(len(ms)) * 5  # large corrections get limited
+    out = C.corrected_site(fc, nv, y, ms, sg)
+    assert out.sum() == pytest.approx(fc.sum(), rel=1e-13)
+    assert out.min() >= -1e-15
