@@ -275,6 +275,9 @@ int lattice_batch_moments(lattice_batch_t* B, const float* f, double* out);
  * cleared), else 0 / EHIP. */
 int lattice_batch_sync(lattice_batch_t* B, int32_t* member_flags);
 
+/* Last detailed error message of the batch handle, or "". */
+const char* lattice_batch_last_error(const lattice_batch_t* B);
+
 int lattice_batch_destroy(lattice_batch_t* B);
 
 /* ===================================================================== *

@@ -37,6 +37,7 @@ struct lattice_batch {
   std::vector<lat::BatchMember> mem;
   int64_t total_cells = 0, total_u = 0;
   hipStream_t stream = nullptr;
+  hipStream_t cap = nullptr;  // private stream the HIP graph is captured on
   hipStream_t side[kSide] = {};
   hipEvent_t ev_fork = nullptr, ev_join[kSide] = {};
   lat::BatchMember* d_mem = nullptr;
@@ -103,14 +104,15 @@ hipError_t build_tiles(lattice_batch_t* B, Cls& c) {
 // Queue n steps (local indices first..first+n-1) of every class, classes on
 // parallel streams (they touch disjoint memory), buffers alternating from
 // parity p0.  The first non-empty class runs on the main stream.
-hipError_t enqueue_steps(lattice_batch_t* B, float* const bufs[2],
-                         const float* u, int first, int64_t n, int p0) {
+hipError_t enqueue_steps(lattice_batch_t* B, hipStream_t main,
+                         float* const bufs[2], const float* u, int first,
+                         int64_t n, int p0) {
   hipStream_t cs[kNumCls] = {};
   int nside = 0, ne = 0;
   for (int c = 0; c < kNumCls; ++c) {
     if (B->cls[c].ntiles == 0) continue;
     if (ne == 0) {
-      cs[c] = B->stream;
+      cs[c] = main;
     } else {
       const int i = (ne - 1) % kSide;
       cs[c] = B->side[i];
@@ -120,7 +122,7 @@ hipError_t enqueue_steps(lattice_batch_t* B, float* const bufs[2],
   }
   hipError_t e = hipSuccess;
   if (nside > 0) {
-    e = hipEventRecord(B->ev_fork, B->stream);
+    e = hipEventRecord(B->ev_fork, main);
     if (e != hipSuccess) return e;
     for (int i = 0; i < nside; ++i) {
       e = hipStreamWaitEvent(B->side[i], B->ev_fork, 0);
@@ -152,7 +154,7 @@ hipError_t enqueue_steps(lattice_batch_t* B, float* const bufs[2],
   for (int i = 0; i < nside; ++i) {
     e = hipEventRecord(B->ev_join[i], B->side[i]);
     if (e != hipSuccess) return e;
-    e = hipStreamWaitEvent(B->stream, B->ev_join[i], 0);
+    e = hipStreamWaitEvent(main, B->ev_join[i], 0);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -267,6 +269,11 @@ int lattice_batch_init(const lattice_member_desc* members, int32_t count,
       rc = LATTICE_EHIP;
       break;
     }
+    if (hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking) !=
+        hipSuccess) {
+      rc = LATTICE_EHIP;
+      break;
+    }
     for (int i = 0; i < kSide; ++i)
       if (hipStreamCreateWithFlags(&B->side[i], hipStreamNonBlocking) !=
               hipSuccess ||
@@ -377,23 +384,28 @@ int lattice_batch_step(lattice_batch_t* B, float* f, const float* u,
         BCHK(B, hipGraphExecDestroy(B->gexec));
         B->gexec = nullptr;
       }
+      // capture on the private stream (the caller's stream may be the
+      // legacy default stream, which cannot be captured); the graph is
+      // then launched on the caller's stream
       hipGraph_t g = nullptr;
-      BCHK(B, hipStreamBeginCapture(B->stream,
-                                    hipStreamCaptureModeThreadLocal));
-      hipError_t e = enqueue_steps(B, bufs, u, 0, graph_steps, 0);
+      BCHK(B, hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
+      hipError_t e = enqueue_steps(B, B->cap, bufs, u, 0, graph_steps, 0);
       if (e == hipSuccess) e = lat::launch_add_int(B->d_base, graph_steps,
-                                                   B->stream);
-      hipError_t e2 = hipStreamEndCapture(B->stream, &g);
+                                                   B->cap);
+      hipError_t e2 = hipStreamEndCapture(B->cap, &g);
       if (e != hipSuccess || e2 != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
         return berr(B, LATTICE_EHIP, "graph capture: %s",
                     hipGetErrorString(e != hipSuccess ? e : e2));
       }
       e = hipGraphInstantiate(&B->gexec, g, nullptr, nullptr, 0);
       (void)hipGraphDestroy(g);
-      if (e != hipSuccess)
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
         return berr(B, LATTICE_EHIP, "graph instantiate: %s",
                     hipGetErrorString(e));
+      }
       B->g_a = bufs[0];
       B->g_b = bufs[1];
       B->g_u = u;
@@ -405,7 +417,8 @@ int lattice_batch_step(lattice_batch_t* B, float* f, const float* u,
     done = reps * graph_steps;
   }
   if (done < nsteps)
-    BCHK(B, enqueue_steps(B, bufs, u, 0, nsteps - done, (int)(done & 1)));
+    BCHK(B, enqueue_steps(B, B->stream, bufs, u, 0, nsteps - done,
+                          (int)(done & 1)));
   return LATTICE_OK;
 }
 
@@ -440,12 +453,17 @@ int lattice_batch_sync(lattice_batch_t* B, int32_t* member_flags) {
   return LATTICE_OK;
 }
 
+const char* lattice_batch_last_error(const lattice_batch_t* B) {
+  return B ? B->msg : "";
+}
+
 int lattice_batch_destroy(lattice_batch_t* B) {
   if (!B) return LATTICE_OK;
   (void)hipStreamSynchronize(B->stream);
   if (B->gexec) (void)hipGraphExecDestroy(B->gexec);
   for (int c = 0; c < kNumCls; ++c)
     if (B->cls[c].d_tiles) (void)hipFree(B->cls[c].d_tiles);
+  if (B->cap) (void)hipStreamDestroy(B->cap);
   for (int i = 0; i < kSide; ++i) {
     if (B->side[i]) (void)hipStreamDestroy(B->side[i]);
     if (B->ev_join[i]) (void)hipEventDestroy(B->ev_join[i]);

@@ -30,7 +30,8 @@ EXPORTS = (
     "lattice_profile_read", "lattice_destroy", "lattice_strerror",
     "lattice_last_error", "lattice_batch_init", "lattice_batch_layout",
     "lattice_batch_tune", "lattice_batch_step", "lattice_batch_moments",
-    "lattice_batch_sync", "lattice_batch_destroy", "lattice_restrict",
+    "lattice_batch_sync", "lattice_batch_destroy", "lattice_batch_last_error",
+    "lattice_restrict",
     "lattice_mlp_create", "lattice_mlp_set_params", "lattice_mlp_get_params",
     "lattice_mlp_samples", "lattice_mlp_grad", "lattice_mlp_train",
     "lattice_mlp_forward", "lattice_mlp_attach", "lattice_mlp_destroy",
@@ -135,6 +136,8 @@ def load_library(path: str = LIB_PATH):
     L.lattice_batch_moments.argtypes = [vp, vp, ctypes.POINTER(dbl)]
     L.lattice_batch_sync.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     L.lattice_batch_destroy.argtypes = [vp]
+    L.lattice_batch_last_error.argtypes = [vp]
+    L.lattice_batch_last_error.restype = ctypes.c_char_p
     pf = ctypes.POINTER(ctypes.c_float)
     L.lattice_restrict.argtypes = [ctypes.c_int32, i64, ctypes.c_int32, vp, vp,
                                    vp]
@@ -399,7 +402,12 @@ class Batch:
 
     def _check(self, rc):
         if rc != OK:
-            raise LatticeError(rc, strerror(rc))
+            msg = strerror(rc)
+            if self._B is not None:
+                d = self.lib.lattice_batch_last_error(self._B).decode()
+                if d:
+                    msg = f"{msg} ({d})"
+            raise LatticeError(rc, msg)
         return rc
 
     def pack_state(self, states):
