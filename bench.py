@@ -209,6 +209,105 @@ def load_traffic(name):
     return t.get("bytes_per_launch")
 
 
+def _rocpd(folder):
+    """The rocpd SQLite database rocprofv3 wrote under folder."""
+    import glob
+    import sqlite3
+    dbs = sorted(glob.glob(os.path.join(folder, "**", "*_results.db"),
+                           recursive=True))
+    if not dbs:
+        sys.exit(f"no rocprofv3 results database under {folder}")
+    return sqlite3.connect(dbs[-1])
+
+
+def _counter(db, counter, pattern):
+    rows = db.execute("select value from counters_collection where "
+                      "counter_name = ? and kernel_name like ? order by "
+                      "dispatch_id", (counter, pattern)).fetchall()
+    if not rows:
+        sys.exit(f"no {counter} rows for kernels like {pattern}")
+    return [r[0] for r in rows]
+
+
+def summarize(args):
+    """Write the kernel-time and HBM-byte summaries of one workload under
+    profiles/ from rocprofv3 output folders.  HBM bytes: the FETCH_SIZE and
+    WRITE_SIZE counters (KiB per dispatch) of the dominant kernel, each
+    scaled by the ratio of known to counted bytes of the plain state copy
+    kernel (k_copy16: reads and writes exactly one state) in the same run."""
+    import statistics
+    w = WORKLOADS[args.workload]
+    trace, fetch, write = (_rocpd(d) for d in args.summarize)
+    kern = "k_step2d" if w["dim"] == 2 else "k_step1d"
+    elem = 8 if w["dtype"] == "f64" else 4
+    ny = w["n"] if w["dim"] == 2 else 1
+    sites = w["n"] * ny
+    cells = sites * w["nv"] ** w["dim"]
+    state = cells * elem
+    algo = 2 * state + w["dim"] * sites * elem
+    name = f"{kern}_{args.workload}"
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    cmd = args.command or "(command not recorded)"
+    top = trace.execute("select name, total_calls, total_duration, average, "
+                        "percentage from top_kernels order by total_duration "
+                        "desc").fetchall()
+    lines = [f"# rocprofv3 --kernel-trace --stats: {args.workload}", "",
+             "command (from the repository root):", "", "    " + cmd, "",
+             "| kernel | calls | total us | average us | % |",
+             "|---|---|---|---|---|"]
+    avg_us = None
+    for nm, calls, tot, avg, pct in top:
+        short = nm.replace("(anonymous namespace)::", "").split("(")[0]
+        lines.append(f"| `{short}` | {calls} | {tot:.1f} | {avg:.1f} | "
+                     f"{pct:.1f} |")
+        if avg_us is None and kern in nm:
+            avg_us = avg
+    with open(os.path.join(ROOT, "profiles", f"{name}_kernel_stats.md"),
+              "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+    f_k = statistics.median(_counter(fetch, "FETCH_SIZE", f"%{kern}%"))
+    w_k = statistics.median(_counter(write, "WRITE_SIZE", f"%{kern}%"))
+    f_c = statistics.median(_counter(fetch, "FETCH_SIZE", "%k_copy16%"))
+    w_c = statistics.median(_counter(write, "WRITE_SIZE", "%k_copy16%"))
+    ff = state / 1024.0 / f_c
+    fw = state / 1024.0 / w_c
+    traffic = (f_k * ff + w_k * fw) * 1024.0
+    out = {"workload": args.workload, "kernel": kern,
+           "kernel_hash": kernel_hash(),
+           "bytes_per_launch": round(traffic),
+           "read_bytes": round(f_k * ff * 1024.0),
+           "write_bytes": round(w_k * fw * 1024.0),
+           "algorithmic_bytes_per_launch": algo,
+           "traffic_over_algorithmic": round(traffic / algo, 5),
+           "fetch_kib_per_dispatch": f_k, "write_kib_per_dispatch": w_k,
+           "copy_fetch_kib": f_c, "copy_write_kib": w_c,
+           "copy_bytes_each_way": state,
+           "fetch_scale": round(ff, 5), "write_scale": round(fw, 5),
+           "trace_avg_launch_us": avg_us, "command": cmd}
+    with open(os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json"),
+              "w") as fh:
+        json.dump(out, fh, indent=1)
+        fh.write("\n")
+    md = [f"# HBM bytes of {kern}: {args.workload}", "",
+          "FETCH_SIZE and WRITE_SIZE are read in separate rocprofv3 --pmc "
+          "runs of the command below (one counter each), per dispatch, "
+          "median over dispatches.  Scale: the plain state copy kernel "
+          "k_copy16 in the same run moves exactly one state each way "
+          f"({state} B).", "", "    " + cmd, "",
+          "| | FETCH_SIZE KiB | WRITE_SIZE KiB |", "|---|---|---|",
+          f"| {kern} | {f_k:.1f} | {w_k:.1f} |",
+          f"| k_copy16 | {f_c:.1f} | {w_c:.1f} |",
+          f"| scale (known / counted) | {ff:.4f} | {fw:.4f} |", "",
+          f"HBM traffic per launch: {traffic:.4g} B "
+          f"(read {f_k * ff * 1024:.4g}, write {w_k * fw * 1024:.4g}); "
+          f"algorithmic {algo} B; ratio {traffic / algo:.4f}."]
+    with open(os.path.join(ROOT, "profiles", f"{name}_hbm_bytes.md"),
+              "w") as fh:
+        fh.write("\n".join(md) + "\n")
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -218,7 +317,20 @@ def main():
                     choices=sorted(WORKLOADS))
     ap.add_argument("--scheme", default="koren", choices=["koren", "upwind"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="N",
+                    help="after the timed region, launch the plain state "
+                         "copy kernel N times on a state-sized buffer (a "
+                         "known-size reference for HBM byte counters)")
+    ap.add_argument("--summarize", nargs=3, metavar=("TRACE", "FETCH", "WRITE"),
+                    help="no GPU run: read three rocprofv3 output folders "
+                         "(--kernel-trace --stats, --pmc FETCH_SIZE, --pmc "
+                         "WRITE_SIZE, each run with --copy-calibration) and "
+                         "write the summaries under profiles/")
+    ap.add_argument("--command", default="",
+                    help="with --summarize: the command line that made them")
     args = ap.parse_args()
+    if args.summarize:
+        return summarize(args)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the lattice update runs on a single "
@@ -276,6 +388,18 @@ def main():
     ev_ms = ev0.elapsed_time(ev1)
     kern_ms, launches = lat.profile_read()
     lat.profile(False)
+    if args.copy_calibration:
+        g = torch.empty_like(f)
+        lat.copy_state(g, f)
+        lat.sync()
+        t1 = time.perf_counter()
+        for _ in range(args.copy_calibration):
+            lat.copy_state(g, f)
+        lat.sync()
+        el = (time.perf_counter() - t1) / args.copy_calibration
+        log(f"bench: state copy kernel {el * 1e6:.1f} us per launch, "
+            f"{2 * cells * elem / el / 1e9:.1f} GB/s")
+        del g
     lat.close()
     log(f"bench: wall {wall * 1e3:.2f} ms, events {ev_ms:.2f} ms, kernel "
         f"{kern_ms:.2f} ms over {launches} launches")

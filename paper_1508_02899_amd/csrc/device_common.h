@@ -28,6 +28,13 @@ __device__ __forceinline__ double koren(double dp, double dm) {
   return med3d(dp, med3d(c, dm, 0.0), 0.0);
 }
 
+__device__ __forceinline__ float fma_t(float a, float b, float c) {
+  return __builtin_fmaf(a, b, c);
+}
+__device__ __forceinline__ double fma_t(double a, double b, double c) {
+  return __builtin_fma(a, b, c);
+}
+
 template <typename T>
 __device__ __forceinline__ T pos(T a) {
   return a > T(0) ? a : T(0);
@@ -58,6 +65,37 @@ __device__ __forceinline__ double lane_read(double v, int src) {
   const int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b >> 32));
   return __longlong_as_double(((long long)hi << 32) |
                               (unsigned int)lo);
+}
+
+// Row-based addressing: the base of a velocity row and the per-cell stride
+// are wave-uniform (scalar registers); each lane adds one 32-bit byte
+// offset.  Every offset inside a row stays below 2^32.
+// The empty asm pins the uniform cell base in scalar registers and keeps
+// the compiler from re-associating it with the lane offset (which would
+// hoist one 64-bit per-lane address per cell out of the row loop).
+#define LAT_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ T row_load(const T* row, uint32_t cell_off,
+                                      uint32_t lane_off) {
+  const char* b = (const char*)row + cell_off;
+  asm("" : "+s"(b));
+  return *(const LAT_GLOBAL T*)((const LAT_GLOBAL char*)b + lane_off);
+}
+template <typename T>
+__device__ __forceinline__ void row_store(T* row, uint32_t cell_off,
+                                          uint32_t lane_off, T v) {
+  char* b = (char*)row + cell_off;
+  asm("" : "+s"(b));
+  *(LAT_GLOBAL T*)((LAT_GLOBAL char*)b + lane_off) = v;
+}
+// Store from the lanes with ok only (the cell base is pinned before the
+// lane mask is applied).
+template <typename T>
+__device__ __forceinline__ void row_store_if(T* row, uint32_t cell_off,
+                                             uint32_t lane_off, T v, bool ok) {
+  char* b = (char*)row + cell_off;
+  asm("" : "+s"(b));
+  if (ok) *(LAT_GLOBAL T*)((LAT_GLOBAL char*)b + lane_off) = v;
 }
 
 }  // namespace lat

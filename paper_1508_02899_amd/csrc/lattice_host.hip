@@ -132,6 +132,7 @@ int lattice_init(const lattice_desc* d, lattice_t** out) {
     return LATTICE_ENOTSUP;
   if (d->dim == 2 && !lat::step2d_supported(d->nv, d->dtype == LATTICE_F64))
     return LATTICE_ENOTSUP;
+
   lattice_t* L = new (std::nothrow) lattice;
   if (!L) return LATTICE_ENOMEM;
   L->d = *d;

@@ -29,6 +29,12 @@ struct StepArgs {
 // Which velocity lattices have a compiled kernel.
 bool step1d_supported(int nv, int f64);
 bool step2d_supported(int nv, int f64);
+// The 2D kernel addresses one vy row (nv planes of nx*ny sites) with 32-bit
+// byte offsets from the row's base (lattice_init already caps a row below
+// 2^31 bytes; the launcher re-checks).
+inline bool step2d_offsets_fit(int nv, int64_t nx, int64_t ny, size_t elem) {
+  return (uint64_t)nv * (uint64_t)nx * (uint64_t)ny * elem < 0xFFFFFFFFull;
+}
 
 hipError_t launch_step1d(const StepArgs& a, hipStream_t s);
 hipError_t launch_step2d(const StepArgs& a, hipStream_t s);

@@ -18,20 +18,34 @@
 //     load row t, pulled from the source sites (x - s(jx-h), y - s(t-h))
 //       [Sec. 2 exact streaming];
 //     A_x: drift along vx inside the row (split upwind fluxes, Koren
-//       correction; 2 halo cells per side from the neighbouring parts);
+//       correction; 1 halo cell per side from the neighbouring parts, and
+//       the two end faces of a part taken from its neighbours);
 //     A_y: drift along vy, streamed: face t-1 is complete once row t is in,
 //       which gives the A_y output of row t-2;
 //     D_x: diffusion along vx on that row (1 halo cell per side);
 //     D_y: diffusion along vy, streamed, giving the final row t-3;
 //     store row t-3.
 //
+// Addressing: each row's base and the per-cell stride are wave-uniform
+// (scalar registers), the per-lane part is one 32-bit VGPR offset (every
+// byte offset inside a vy row stays below 2^32 - 1; the host checks this).  Rows 3..NV-1 run in a loop without the row-range selects
+// of the first and last rows.
+//
 // The per-site order A_x, A_y, D_x, D_y is the paper's "force, then
 // diffusion" split by velocity axis.  Zero flux through the outer faces of
 // the velocity square; cells outside it are empty for the limiter.
 #pragma once
 
+#include <type_traits>
+
 #include "device_common.h"
 #include "lattice_internal.h"
+
+// No implicit multiply-add contraction in this file: interior and edge tiles
+// are separate instantiations, and a site must get the same bits in either
+// (the result is invariant under translation of the lattice).  Fused
+// multiply-adds are written out where they are meant.
+#pragma clang fp contract(off)
 
 namespace lat {
 
@@ -54,46 +68,55 @@ struct Step2D {
 
   // One row t: c holds row t after streaming (when t < NV).  Reads state
   // `in`, writes state `out`; stores the finished row t-3 when t >= 3.
+  // STEADY: 3 <= t < NV, where every row-range condition below holds, so
+  // the steady loop carries no selects for them.
+  // emit(i, v) receives cell i of the finished row t-3.
+  template <bool STEADY, typename Emit>
   __device__ __forceinline__ static void row(
       const int t, const T (&c)[W], const YState<T, W>& in,
-      YState<T, W>& out, const T (&nxp)[W + 4], const T (&nxm)[W + 4],
+      YState<T, W>& out, const T (&nxp)[W + 2], const T (&nxm)[W + 2],
       const T ay, const T beta, const T D, const bool first, const bool last,
-      const int lane_l, const int lane_r, T* __restrict__ obase,
-      const size_t rowpitch, const uint32_t slot_bytes,
-      const uint32_t lane_off, const bool store_ok) {
+      const int lane_l, const int lane_r, Emit&& emit) {
     T q[W];  // row t after A_x (zero past the last row)
-    if (t < NV) {
-      T cc[W + 4];  // cells -2 .. W+1 of this lane's slice
+    if (STEADY || t < NV) {
+      T cc[W + 2];  // cells -1 .. W of this lane's slice
 #pragma unroll
-      for (int i = 0; i < W; ++i) cc[i + 2] = c[i];
+      for (int i = 0; i < W; ++i) cc[i + 1] = c[i];
       if (P > 1) {
-        const T l2 = lane_read(c[W - 3], lane_l);
         const T l1 = lane_read(c[W - 2], lane_l);
         const T r0 = lane_read(c[1], lane_r);
-        const T r1 = lane_read(c[2], lane_r);
-        cc[0] = first ? T(0) : l2;
-        cc[1] = first ? T(0) : l1;
-        cc[W + 2] = last ? T(0) : r0;
-        cc[W + 3] = last ? T(0) : r1;
+        cc[0] = first ? T(0) : l1;
+        cc[W + 1] = last ? T(0) : r0;
       } else {
-        cc[0] = cc[1] = cc[W + 2] = cc[W + 3] = T(0);
+        cc[0] = cc[W + 1] = T(0);
       }
-      T gp[W + 4], gm[W + 4];
+      T gp[W + 2], gm[W + 2];
 #pragma unroll
-      for (int i = 0; i < W + 4; ++i) {
+      for (int i = 0; i < W + 2; ++i) {
         gp[i] = nxp[i] * cc[i];
         gm[i] = nxm[i] * cc[i];
       }
-      T F[W + 1];  // face f between cells f-1 and f of the slice
+      // face f lies between cells f-1 and f; this lane computes the inner
+      // faces 1..W-1.  Face 0 is the left part's face W-1 and face W the
+      // right part's face 1 (same inputs, same operations), or closed at
+      // the ends of the velocity axis.
+      T F[W + 1];
 #pragma unroll
-      for (int f = 0; f <= W; ++f) {
-        T fl = gp[f + 1] + gm[f + 2];
-        if (KOREN)
-          fl += koren(gp[f + 2] - gp[f + 1], gp[f + 1] - gp[f]) +
-                koren(gm[f + 1] - gm[f + 2], gm[f + 2] - gm[f + 3]);
-        if (f == 0) fl = first ? T(0) : fl;  // face 0 of the velocity square
-        if (f == W) fl = last ? T(0) : fl;   // face NV
+      for (int f = 1; f < W; ++f) {
+        T fl = gp[f] + gm[f + 1];
+        if (KOREN) {
+          fl += koren(gp[f + 1] - gp[f], gp[f] - gp[f - 1]) +
+                koren(gm[f] - gm[f + 1], gm[f + 1] - gm[f + 2]);
+        }
         F[f] = fl;
+      }
+      if (P > 1) {
+        const T fl = lane_read(F[W - 1], lane_l);
+        const T fr = lane_read(F[1], lane_r);
+        F[0] = first ? T(0) : fl;
+        F[W] = last ? T(0) : fr;
+      } else {
+        F[0] = F[W] = T(0);
       }
 #pragma unroll
       for (int i = 0; i < W; ++i) q[i] = c[i] - (F[i + 1] - F[i]);
@@ -103,10 +126,10 @@ struct Step2D {
     }
 
     // ---- A_y (streamed): g+ flux of face t, g- flux of face t-1 ----------
-    const T nu = ay - beta * (T)(t - H);
+    const T nu = fma_t(-beta, (T)(t - H), ay);
     const T nyp = pos(nu), nym = neg(nu);
-    const bool fpv = t >= 1 && t <= NV - 1;
-    const bool fmv = t >= 2 && t <= NV;
+    const bool fpv = STEADY || (t >= 1 && t <= NV - 1);
+    const bool fmv = STEADY || (t >= 2 && t <= NV);
     T a[W];
 #pragma unroll
     for (int i = 0; i < W; ++i) {
@@ -114,11 +137,11 @@ struct Step2D {
       const T dpp = gpv - in.gp1[i];
       T Fp = in.gp1[i];
       if (KOREN) Fp += koren(dpp, in.dpp1[i]);
-      Fp = fpv ? Fp : T(0);
+      if (!STEADY) Fp = fpv ? Fp : T(0);
       const T em = in.gm1[i] - gmv;
       T Fm = in.gm1[i];
       if (KOREN) Fm += koren(in.em1[i], em);
-      Fm = fmv ? Fm : T(0);
+      if (!STEADY) Fm = fmv ? Fm : T(0);
       const T Fface = in.Fp1[i] + Fm;  // total flux through face t-1
       a[i] = in.acc2[i] - Fface;       // A_y output of row t-2
       out.acc2[i] = in.c1[i] + Fface;
@@ -130,7 +153,7 @@ struct Step2D {
       out.em1[i] = em;
     }
 
-    if (t >= 2) {
+    if (STEADY || t >= 2) {
       // ---- D_x on row t-2 (halos a_{-1}, a_W) ------------------------------
       T al = T(0), ar = T(0);
       if (P > 1) {
@@ -149,17 +172,14 @@ struct Step2D {
         if (f == W) d = last ? T(0) : d;
         dxf[f] = d;
       }
-      // ---- D_y (streamed) and store row t-3 ------------------------------
+      // ---- D_y (streamed), giving row t-3 ----------------------------------
       const int r = t - 2;  // row of b
-      const bool dv = r >= 1 && r <= NV - 1;
-      T* orow = obase + (size_t)(r - 1) * rowpitch;
+      const bool dv = STEADY || (r >= 1 && r <= NV - 1);
 #pragma unroll
       for (int i = 0; i < W; ++i) {
-        const T b = a[i] + D * (dxf[i] - dxf[i + 1]);
+        const T b = fma_t(D, dxf[i] - dxf[i + 1], a[i]);
         const T del = dv ? in.a3[i] - b : T(0);
-        if (r >= 1 && store_ok)
-          *(T*)((char*)orow + (size_t)(i * slot_bytes) + lane_off) =
-              in.a3[i] + D * (in.del3[i] - del);
+        if (STEADY || r >= 1) emit(i, fma_t(D, in.del3[i] - del, in.a3[i]));
         out.a3[i] = b;
         out.del3[i] = del;
       }
@@ -173,6 +193,39 @@ struct Step2D {
   }
 };
 
+// Output staging of a workgroup (P > 1).  The 4 wavefronts of a workgroup
+// own G = 4S consecutive sites of one spatial row; a wavefront's direct
+// stores would write S-site pieces of P planes per instruction.  Instead
+// each finished row goes to LDS and the workgroup stores it plane by plane,
+// 64 consecutive elements per store instruction.  The plane stride is
+// padded so that the P parts of a wavefront write to disjoint LDS banks.
+template <typename T, int NV, int P>
+struct OutStage {
+  static constexpr int S = 64 / P;
+  static constexpr int G = 4 * S;          // sites per workgroup
+  static constexpr int W = (NV - 1) / P + 1;
+  static constexpr int DW = sizeof(T) / 4;  // dwords per element
+  static constexpr int pad() {
+    for (int pd = 0; pd < 64; ++pd) {
+      bool used[64] = {};
+      bool ok = true;
+      for (int p = 0; p < P && ok; ++p)
+        for (int sl = 0; sl < S && ok; ++sl)
+          for (int d = 0; d < DW && ok; ++d) {
+            const int bank =
+                ((p * (W - 1) * (G + pd) + sl) * DW + d) % 64;
+            if (used[bank]) ok = false;
+            used[bank] = true;
+          }
+      if (ok || P * S * DW > 64) return pd;
+    }
+    return 0;
+  }
+  static constexpr int STRIDE = G + pad();      // elements per plane
+  static constexpr int SIZE = NV * STRIDE;      // elements per buffer
+  static constexpr int K = (NV + P - 1) / P;    // stores per thread per row
+};
+
 // INTERIOR: every source site of the tile lies inside [0, nx) without
 // wrapping, so all cells of a row load from one uniform base plus one
 // per-lane offset (plus a uniform per-cell stride); otherwise each cell
@@ -180,13 +233,15 @@ struct Step2D {
 template <typename T, int NV, int P, bool KOREN, bool INTERIOR>
 __device__ __forceinline__ void step2d_tile(
     const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict__ u,
-    int nx, int ny, int shift, int xstep, int xoff0, int ystep, int yoff0,
-    T alpha_scale, T beta, T D, int x0, int y) {
+    T* __restrict__ stage, int nx, int ny, int shift, int xstep, int xoff0,
+    int ystep, int yoff0, T alpha_scale, T beta, T D, int xg, int w, int y) {
   using K = Step2D<T, NV, P, KOREN>;
-  constexpr int W = K::W, S = K::S, H = K::H;
+  using O = OutStage<T, NV, P>;
+  constexpr int W = K::W, S = K::S, H = K::H, G = O::G;
   const int lane = (int)threadIdx.x & 63;
   const int p = lane / S;
   const int sl = lane - p * S;
+  const int x0 = xg * G + w * S;  // first site of this wavefront
   int x = x0 + sl;
   const bool active = x < nx;
   if (!active) x = nx - 1;  // duplicate a real site; never stored
@@ -199,16 +254,16 @@ __device__ __forceinline__ void step2d_tile(
   const T ax = u[(size_t)y * nx + x] * alpha_scale;
   const T ay = u[nxy + (size_t)y * nx + x] * alpha_scale;
 
-  // vx drift of cells -2 .. W+1 (index + 2), cell widths per step
-  T nxp[W + 4], nxm[W + 4];
+  // vx drift of cells -1 .. W (index + 1), cell widths per step
+  T nxp[W + 2], nxm[W + 2];
 #pragma unroll
-  for (int i = 0; i < W + 4; ++i) {
-    const T nu = ax - beta * (T)(jx0 + i - 2 - H);
+  for (int i = 0; i < W + 2; ++i) {
+    const T nu = fma_t(-beta, (T)(jx0 + i - 1 - H), ax);
     nxp[i] = pos(nu);
     nxm[i] = neg(nu);
   }
 
-  // load offsets (bytes) of the W cells inside one vy row
+  // byte offsets of the W cells of one vy row from the row's base
   uint32_t koff[INTERIOR ? 1 : W];
   uint32_t cell_stride = 0;  // INTERIOR: bytes between consecutive cells
   if (INTERIOR) {
@@ -232,21 +287,74 @@ __device__ __forceinline__ void step2d_tile(
     }
   }
   const uint32_t slot_bytes = (uint32_t)(nxy * sizeof(T));
-  const uint32_t store_lane = (uint32_t)(((size_t)jx0 * nxy + sl) * sizeof(T));
-  T* obase = fout + (size_t)y * nx + x0;
   const T* fbase = INTERIOR ? fin + x0 + (size_t)shift * H : fin;
 
   auto load_row = [&](int t, int ys, T (&c)[W]) {
-    const char* src = (const char*)(fbase + (size_t)t * rowpitch +
-                                    (size_t)ys * nx);
+    const T* src = fbase + (size_t)t * rowpitch + (size_t)ys * nx;
 #pragma unroll
-    for (int i = 0; i < W; ++i) {
-      if (INTERIOR)
-        c[i] = *(const T*)(src + (size_t)(i * cell_stride) + koff[0]);
-      else
-        c[i] = *(const T*)(src + koff[i]);
+    for (int i = 0; i < W; ++i)
+      c[i] = INTERIOR ? row_load(src, (uint32_t)i * cell_stride, koff[0])
+                      : row_load(src, 0u, koff[i]);
+  };
+
+  // Output of row t (the finished row t-3).  P == 1: a wavefront already
+  // stores 64 consecutive sites per instruction.  P > 1: cells go to the
+  // LDS buffer of t's parity; flush() then stores the workgroup's row.
+  // Lanes past the end of the spatial row hold a duplicate of site nx-1
+  // (same inputs, same operations, so the same bits) and store it there:
+  // every store is unconditional, which keeps the memory-counter waits
+  // exact.
+  // P == 1: offsets from the start of spatial row y (x is the clamped site,
+  // so the offset is never negative, also for wavefronts past the end)
+  const uint32_t store_lane =
+      (uint32_t)(((size_t)jx0 * nxy + (size_t)x) * sizeof(T));
+  T* const orow0 = fout + (size_t)y * nx;
+  T* const sbase = stage + jx0 * O::STRIDE + w * S + sl;  // P > 1
+  const int tid = (int)threadIdx.x;
+  // flush: thread tid stores plane fj0 + P k, site fs of the workgroup
+  const int fj0 = G >= 64 ? __builtin_amdgcn_readfirstlane(tid / G) : tid / G;
+  const int fs = tid - (tid / G) * G;
+  const int fx = min(xg * G + fs, nx - 1);
+  const uint32_t flane =
+      (uint32_t)(((size_t)fj0 * nxy + (size_t)(fx - xg * G)) * sizeof(T));
+  T* const frow0 = fout + (size_t)y * nx + (size_t)xg * G;
+  auto flush = [&](int t) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    const T* sb = stage + (t & 1) * O::SIZE + fj0 * O::STRIDE + fs;
+    T* orow = frow0 + (size_t)(t - 3) * rowpitch;
+    constexpr int KL = O::K - 1;  // the last round covers planes < NV only
+    T v[O::K];  // all LDS reads first, then the stores
+#pragma unroll
+    for (int k = 0; k < KL; ++k) v[k] = sb[k * P * O::STRIDE];
+    const bool last_in = fj0 + P * KL < NV;
+    v[KL] = last_in ? sb[KL * P * O::STRIDE] : T(0);
+#pragma unroll
+    for (int k = 0; k < KL; ++k)
+      row_store(orow, (uint32_t)(k * P) * slot_bytes, flane, v[k]);
+    row_store_if(orow, (uint32_t)(KL * P) * slot_bytes, flane, v[KL],
+                 last_in);
+  };
+  auto run_row = [&](auto steady, int t, const T (&c)[W],
+                     const YState<T, W>& sin, YState<T, W>& sout) {
+    if (P == 1) {
+      T* orow = orow0 + (size_t)(t - 3) * rowpitch;
+      K::template row<decltype(steady)::value>(
+          t, c, sin, sout, nxp, nxm, ay, beta, D, first, last, lane_l,
+          lane_r, [&](int i, T v) {
+            row_store(orow, (uint32_t)i * slot_bytes, store_lane, v);
+          });
+    } else {
+      T* sb = sbase + (t & 1) * O::SIZE;
+      K::template row<decltype(steady)::value>(
+          t, c, sin, sout, nxp, nxm, ay, beta, D, first, last, lane_l,
+          lane_r, [&](int i, T v) { sb[i * O::STRIDE] = v; });
+      if (decltype(steady)::value || t >= 3) flush(t);
     }
   };
+  using steady_t = std::integral_constant<bool, true>;
+  using edge_t = std::integral_constant<bool, false>;
 
   YState<T, W> s0, s1;
 #pragma unroll
@@ -259,69 +367,97 @@ __device__ __forceinline__ void step2d_tile(
   if (ys >= ny) ys -= ny;
   auto next_ys = [&](int v) {
     v -= ystep;
-    return v < 0 ? v + ny : v;
+    return __builtin_amdgcn_readfirstlane(v < 0 ? v + ny : v);
   };
 
+  // rows 0..2 fill the streamed state; rows 3..NV-1 are the steady part
+  // (NV - 3 rows, an even count, processed in pairs); rows NV..NV+2 drain
+  // it.  Row t+1 is loaded before row t is processed.  The first and the
+  // last steady pair are peeled so that the loop body issues the same
+  // loads and stores on every trip and on entry: the memory counter waits
+  // then only ever wait for the row about to be used, never for the
+  // stores issued after it.
   T bufA[W], bufB[W];
   load_row(0, ys, bufA);
   ys = next_ys(ys);
-  int t = 0;
-#pragma unroll 1
-  for (; t + 1 < NV + 3; t += 2) {
-    if (t + 1 < NV) {
-      load_row(t + 1, ys, bufB);
-      ys = next_ys(ys);
-    }
-    K::row(t, bufA, s0, s1, nxp, nxm, ay, beta, D, first, last, lane_l,
-           lane_r, obase, rowpitch, slot_bytes, store_lane, INTERIOR || active);
-    if (t + 2 < NV) {
-      load_row(t + 2, ys, bufA);
-      ys = next_ys(ys);
-    }
-    K::row(t + 1, bufB, s1, s0, nxp, nxm, ay, beta, D, first, last, lane_l,
-           lane_r, obase, rowpitch, slot_bytes, store_lane, INTERIOR || active);
+  load_row(1, ys, bufB);
+  ys = next_ys(ys);
+  run_row(edge_t(), 0, bufA, s0, s1);
+  load_row(2, ys, bufA);
+  ys = next_ys(ys);
+  run_row(edge_t(), 1, bufB, s1, s0);
+  if (NV > 3) {
+    load_row(3, ys, bufB);
+    ys = next_ys(ys);
   }
-  if (t < NV + 3)
-    K::row(t, bufA, s0, s1, nxp, nxm, ay, beta, D, first, last, lane_l,
-           lane_r, obase, rowpitch, slot_bytes, store_lane, INTERIOR || active);
+  run_row(edge_t(), 2, bufA, s0, s1);
+  // steady pair (t, t+1): row t is in bufB, state in s1
+  auto pair = [&](int t, bool load2) {
+    load_row(t + 1, ys, bufA);
+    ys = next_ys(ys);
+    run_row(steady_t(), t, bufB, s1, s0);
+    if (load2) {
+      load_row(t + 2, ys, bufB);
+      ys = next_ys(ys);
+    }
+    run_row(steady_t(), t + 1, bufA, s0, s1);
+  };
+  if (NV >= 7) {
+    pair(3, true);
+#pragma unroll 1
+    for (int t = 5; t <= NV - 4; t += 2) pair(t, true);
+    pair(NV - 2, false);
+  } else if (NV == 5) {
+    pair(3, false);
+  }
+  run_row(edge_t(), NV, bufB, s1, s0);
+  run_row(edge_t(), NV + 1, bufB, s0, s1);
+  run_row(edge_t(), NV + 2, bufB, s1, s0);
 }
 
+// One workgroup = 4 wavefronts = G consecutive sites of spatial row y.  All
+// four run the same row sequence (the staged stores synchronise them once
+// per row), so none may leave early; wavefronts past the end of the row
+// compute on duplicated sites and store nothing.
 template <typename T, int NV, int P, bool KOREN>
 __global__ __launch_bounds__(256) void k_step2d(
     const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict__ u,
     const int* __restrict__ flag, int nx, int ny, int shift, int xstep,
-    int xoff0, int ystep, int yoff0, T alpha_scale, T beta, T D, int ntx,
-    int ntiles, int nblocks) {
+    int xoff0, int ystep, int yoff0, T alpha_scale, T beta, T D, int ngx,
+    int nblocks) {
+  using O = OutStage<T, NV, P>;
   constexpr int S = 64 / P;
   constexpr int H = (NV - 1) / 2;
-  if (*flag != 0) return;
-  // tile index is uniform per wavefront; keep it (and all row bases) in
-  // scalar registers
-  const int tile = __builtin_amdgcn_readfirstlane(
-      xcd_remap(blockIdx.x, nblocks) * 4 + ((int)threadIdx.x >> 6));
-  if (tile >= ntiles) return;  // whole wavefront idle
-  const int y = tile / ntx;
-  const int x0 = (tile - y * ntx) * S;
+  __shared__ T stage[P > 1 ? 2 * O::SIZE : 1];
+  if (*flag != 0) return;  // uniform over the grid
+  const int b = xcd_remap(blockIdx.x, nblocks);
+  const int y = b / ngx;
+  const int xg = b - y * ngx;
+  const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const int x0 = xg * O::G + w * S;
   const bool interior = x0 + S <= nx && x0 - shift * H >= 0 &&
                         x0 + S - 1 + shift * H <= nx - 1;
   if (interior)
-    step2d_tile<T, NV, P, KOREN, true>(fin, fout, u, nx, ny, shift, xstep,
-                                       xoff0, ystep, yoff0, alpha_scale, beta,
-                                       D, x0, y);
+    step2d_tile<T, NV, P, KOREN, true>(fin, fout, u, stage, nx, ny, shift,
+                                       xstep, xoff0, ystep, yoff0,
+                                       alpha_scale, beta, D, xg, w, y);
   else
-    step2d_tile<T, NV, P, KOREN, false>(fin, fout, u, nx, ny, shift, xstep,
-                                        xoff0, ystep, yoff0, alpha_scale,
-                                        beta, D, x0, y);
+    step2d_tile<T, NV, P, KOREN, false>(fin, fout, u, stage, nx, ny, shift,
+                                        xstep, xoff0, ystep, yoff0,
+                                        alpha_scale, beta, D, xg, w, y);
 }
 
 template <typename T, int NV, int P>
 hipError_t launch_step2d_nv(const StepArgs& a, hipStream_t s) {
-  constexpr int S = 64 / P;
+  constexpr int G = OutStage<T, NV, P>::G;
+  if (!step2d_offsets_fit(NV, a.nx, a.ny, sizeof(T)))
+    return hipErrorNotSupported;
   const int nx = (int)a.nx, ny = (int)a.ny;
   const int H = (NV - 1) / 2;
-  const int ntx = (nx + S - 1) / S;
-  const int ntiles = ntx * ny;
-  const int nblocks = (ntiles + 3) / 4;
+  const int ngx = (nx + G - 1) / G;
+  const int64_t nb = (int64_t)ngx * ny;
+  if (nb > 0x7FFFFFFF) return hipErrorInvalidValue;
+  const int nblocks = (int)nb;
   const int xstep = a.shift % nx;
   const int xoff0 = (int)(((int64_t)a.shift * H) % nx);
   const int ystep = a.shift % ny;
@@ -331,12 +467,12 @@ hipError_t launch_step2d_nv(const StepArgs& a, hipStream_t s) {
     hipLaunchKernelGGL((k_step2d<T, NV, P, true>), dim3(nblocks), dim3(256), 0,
                        s, (const T*)a.fin, (T*)a.fout, (const T*)a.u, a.flag,
                        nx, ny, a.shift, xstep, xoff0, ystep, yoff0, as, be, D,
-                       ntx, ntiles, nblocks);
+                       ngx, nblocks);
   else
     hipLaunchKernelGGL((k_step2d<T, NV, P, false>), dim3(nblocks), dim3(256),
                        0, s, (const T*)a.fin, (T*)a.fout, (const T*)a.u,
                        a.flag, nx, ny, a.shift, xstep, xoff0, ystep, yoff0, as,
-                       be, D, ntx, ntiles, nblocks);
+                       be, D, ngx, nblocks);
   return hipGetLastError();
 }
 
