@@ -95,7 +95,7 @@ def cpu_baseline(w, name, dx, dv, dt, tau_p):
     L = 2 * math.pi
     if w["dim"] == 2:
         m = min(w["n"], 256 if w["nv"] <= 33 else 128)
-        steps = 2
+        steps = 4
         u = make_flow(w, 1, dt, np.float32)[:, :, :m, :m]
         f0 = inputs.gaussian_ic(2, m, w["nv"], dx, dv, ny=m)
         sample = (f"{m}x{m} sites (a crop of the {w['n']}x{w['n']} lattice) "

@@ -150,6 +150,16 @@ int lattice_step(lattice_t* L, void* f, const void* u, int64_t n_u_slices,
                  double tau_p, double kappa, double dt, int64_t nsteps);
 
 /*
+ * The collision part of lattice_step alone: the same nsub sub-steps of
+ * drift and diffusion (Sec. 2 operator splitting) with the streaming left
+ * out, and no learned correction.  Same arguments, checks and semantics as
+ * lattice_step.  A step equals streaming followed by this.  Used to build
+ * velocity-space training targets for the coarse lattice.
+ */
+int lattice_collide(lattice_t* L, void* f, const void* u, int64_t n_u_slices,
+                    double tau_p, double kappa, double dt, int64_t nsteps);
+
+/*
  * FP64 moments of f (device, read-only) for time step dt (which fixes dv),
  * reduced on the GPU in a fixed order (deterministic) into *out (host).
  * Synchronous: waits for the stream.  Returns ECFL if the sticky CFL flag
@@ -165,6 +175,21 @@ int lattice_moments(lattice_t* L, const void* f, double dt,
  * EINVAL on NULL pointers or dt <= 0.
  */
 int lattice_density(lattice_t* L, const void* f, double dt, double* rho);
+
+/*
+ * Second moment of the coarse-grained density (Sec. 3.1 defines rho_r as
+ * the mass in a window of size r; Sec. 3.2 evaluates it on a tiling of
+ * boxes of size r; Sec. 4.2.1 studies <rho_r^2> against r).  Tilings with
+ * boxes of r = 2^k lattice spacings per direction, k = 0..levels-1, of
+ * the density rho (device, [ny][nx] FP64, e.g. from lattice_density):
+ *   out[k] = <rho_r^2> = N_b sum_b m_b^2 / (sum_b m_b)^2,
+ * m_b the density summed over box b, N_b the number of boxes (so that
+ * <rho_r> = 1).  out: host, levels doubles.  nx (and ny in 2D) must be
+ * multiples of 2^(levels-1); levels <= 32.  FP64 sums in a fixed order
+ * (bit-reproducible).  Synchronous; allocates a temporary device
+ * workspace.  EINVAL, ENOMEM, ENONFINITE (zero or non-finite mass), EHIP.
+ */
+int lattice_rho_r2(lattice_t* L, const double* rho, int levels, double* out);
 
 /*
  * Largest drift CFL number of Eq. 3 and the diffusion number of Eq. 4 for
@@ -319,9 +344,12 @@ int lattice_mlp_get_params(lattice_mlp_t* M, float* host_params);
  * later (both device [289][ny][nx]), the residual r = f_true - f_pred is
  * written as the face fluxes of least norm with -div G = r, and for every
  * interior face (x-faces (row, k) then y-faces (k, column); 544 per site)
- * X[8] = features of f_pred, t = sign * G / m_s, w = m_s.  Device outputs.
- * Asynchronous.  EINVAL, ENOTSUP, EHIP. */
+ * X[8] = features of f_pred, t = sign * G / m_s, w = m_s.  Faces whose
+ * stencil mass m_s is below rel_eps times the site mass (0 <= rel_eps < 1)
+ * or below 1e-30 get w = 0, t = 0 and zero stencil features.  Device
+ * outputs.  Asynchronous.  EINVAL, ENOTSUP, EHIP. */
 int lattice_mlp_samples(lattice_t* L, double dt, double tau_p, double St,
+                        double rel_eps,
                         const float* f_pred, const float* f_true,
                         const float* u, const int32_t* sites, int64_t nsites,
                         float* X, float* t, float* w);

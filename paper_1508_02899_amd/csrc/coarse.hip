@@ -33,20 +33,25 @@ __device__ __forceinline__ float bf2f(uint16_t b) {
 }
 __device__ __forceinline__ float qbf(float f) { return bf2f(f2bf(f)); }
 
-// GELU, tanh form (Hendrycks & Gimpel 2016), and its derivative.
-__device__ __forceinline__ float gelu(float z) {
+// GELU, tanh form (Hendrycks & Gimpel 2016), and its derivative, written
+// with the identity 0.5 (1 + tanh(y)) = 1 / (1 + exp(-2y)): one exponential
+// and one approximate reciprocal (1 ulp) per value, no division.  For very
+// negative z, exp overflows to +inf and the reciprocal gives 0 (gelu -> -0).
+__device__ __forceinline__ float gelu_sig(float z, float z2) {
   const float a = 0.7978845608028654f, c = 0.044715f;
-  const float inner = a * z * (1.0f + c * z * z);
-  const float t = 1.0f - 2.0f / (1.0f + __expf(2.0f * inner));
-  return 0.5f * z * (1.0f + t);
+  const float k = -2.0f * 1.4426950408889634f;  // -2 log2(e)
+  const float y = a * z * __builtin_fmaf(c, z2, 1.0f);
+  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(k * y));
+}
+__device__ __forceinline__ float gelu(float z) {
+  return z * gelu_sig(z, z * z);
 }
 __device__ __forceinline__ float gelu_d(float z, float* dg) {
   const float a = 0.7978845608028654f, c = 0.044715f;
   const float z2 = z * z;
-  const float inner = a * z * (1.0f + c * z2);
-  const float t = 1.0f - 2.0f / (1.0f + __expf(2.0f * inner));
-  *dg = 0.5f * (1.0f + t) + 0.5f * z * (1.0f - t * t) * a * (1.0f + 3.0f * c * z2);
-  return 0.5f * z * (1.0f + t);
+  const float sg = gelu_sig(z, z2);
+  *dg = sg + 2.0f * z * sg * (1.0f - sg) * a * __builtin_fmaf(3.0f * c, z2, 1.0f);
+  return z * sg;
 }
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
@@ -204,6 +209,8 @@ __device__ __forceinline__ void face_feat(LINE line, int nv, int k, float u,
 // being the Neumann Laplacian of the velocity square, diagonal in the
 // cosine (DCT-II) basis with eigenvalues lam_kx + lam_ky,
 // lam_k = 4 sin^2(pi k / (2 nv)).
+constexpr float kMinStencilMass = 1e-30f;  // 1 / m_s stays finite above
+
 template <int NV>
 __global__ __launch_bounds__(320) void k_flux_samples(
     CoarseGeom g, const float* __restrict__ fp, const float* __restrict__ ft,
@@ -229,7 +236,13 @@ __global__ __launch_bounds__(320) void k_flux_samples(
     const float sk = sinpif((float)k / (2.0f * NV));
     lam[k] = 4.0f * sk * sk;
   }
+  __shared__ float msite;
   __syncthreads();
+  if (tid == 0) {  // site mass, in a fixed order
+    float m = 0.f;
+    for (int i = 0; i < N2; ++i) m += pred[i];
+    msite = m;
+  }
   // forward transform along x, then y
   for (int i = tid; i < N2; i += bd) {
     const int jy = i / NV, kx = i - jy * NV;
@@ -277,15 +290,17 @@ __global__ __launch_bounds__(320) void k_flux_samples(
       face_feat(line, NV, k, uy, g, st, &ms, &sg, &anu);
       G = r[(k - 1) * NV + jx] - r[k * NV + jx];
     }
-    const float inv = ms > 0.f ? 1.0f / ms : 0.f;
+    // faces with (next to) no mass in the stencil carry no sample weight
+    const bool use = ms > kMinStencilMass && ms >= g.line_eps * msite;
+    const float inv = use ? 1.0f / ms : 0.f;
     float* x = X + (base + f) * kNF;
 #pragma unroll
     for (int i = 0; i < 5; ++i) x[i] = st[i] * inv;
     x[5] = anu;
     x[6] = g.log_st;
     x[7] = 0.f;
-    T[base + f] = sg * G * inv;
-    Wt[base + f] = ms;
+    T[base + f] = use ? sg * G * inv : 0.f;
+    Wt[base + f] = use ? ms : 0.f;
   }
 }
 

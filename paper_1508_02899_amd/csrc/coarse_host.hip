@@ -130,12 +130,12 @@ int lattice_mlp_get_params(lattice_mlp_t* M, float* host_params) {
 }
 
 int lattice_mlp_samples(lattice_t* L, double dt, double tau_p, double St,
-                        const float* f_pred, const float* f_true,
+                        double rel_eps, const float* f_pred, const float* f_true,
                         const float* u, const int32_t* sites, int64_t nsites,
                         float* X, float* t, float* w) {
   if (!L || !f_pred || !f_true || !u || !sites || !X || !t || !w ||
       nsites < 1 || nsites > (1 << 30) || !(dt > 0) || !(tau_p > 0) ||
-      !(St > 0))
+      !(St > 0) || !(rel_eps >= 0) || !(rel_eps < 1))
     return LATTICE_EINVAL;
   const lattice_desc& d = L->d;
   if (d.dim != 2 || d.nv != 17 || d.dtype != LATTICE_F32)
@@ -148,7 +148,7 @@ int lattice_mlp_samples(lattice_t* L, double dt, double tau_p, double St,
   g.dv = (float)dv;
   g.nu_scale = (float)(dt / (tau_p * dv));
   g.log_st = (float)log(St);
-  g.line_eps = 0.f;
+  g.line_eps = (float)rel_eps;
   if (lat::launch_flux_samples(g, f_pred, f_true, u, sites, (int)nsites, X, t,
                                w, L->stream) != hipSuccess)
     return LATTICE_EHIP;

@@ -166,8 +166,11 @@ int lattice_init(const lattice_desc* d, lattice_t** out) {
   return LATTICE_OK;
 }
 
-int lattice_step(lattice_t* L, void* f, const void* u, int64_t n_u_slices,
-                 double tau_p, double kappa, double dt, int64_t nsteps) {
+// One call of nsteps steps; stream == false leaves out the streaming (every
+// pass has shift 0) and the learned correction: the collision part alone.
+static int advance(lattice_t* L, void* f, const void* u, int64_t n_u_slices,
+                   double tau_p, double kappa, double dt, int64_t nsteps,
+                   bool stream) {
   if (!L) return LATTICE_EINVAL;
   L->msg[0] = 0;
   const lattice_desc& d = L->d;
@@ -245,7 +248,7 @@ int lattice_step(lattice_t* L, void* f, const void* u, int64_t n_u_slices,
     for (int64_t ps = 0; ps < passes_per_step; ++ps, ++k) {
       a.fin = bufs[k & 1];
       a.fout = bufs[(k + 1) & 1];
-      a.shift = ps == 0 ? d.vstride : 0;
+      a.shift = (ps == 0 && stream) ? d.vstride : 0;
       a.nsub_inline = d.dim == 1 ? d.nsub : 1;
       HIPCHK(L, record_pair(L, false));
       hipError_t e = d.dim == 1 ? lat::launch_step1d(a, L->stream)
@@ -253,10 +256,20 @@ int lattice_step(lattice_t* L, void* f, const void* u, int64_t n_u_slices,
       if (e != hipSuccess) return hip_err(L, e, "step kernel launch");
       HIPCHK(L, record_pair(L, true));
     }
-    if (L->mlp)  // learned face-flux correction of the coarse lattice
+    if (L->mlp && stream)  // learned face-flux correction (coarse lattice)
       HIPCHK(L, lat::apply_mlp(L, bufs[k & 1], a.u, dt, tau_p));
   }
   return LATTICE_OK;
+}
+
+int lattice_step(lattice_t* L, void* f, const void* u, int64_t n_u_slices,
+                 double tau_p, double kappa, double dt, int64_t nsteps) {
+  return advance(L, f, u, n_u_slices, tau_p, kappa, dt, nsteps, true);
+}
+
+int lattice_collide(lattice_t* L, void* f, const void* u, int64_t n_u_slices,
+                    double tau_p, double kappa, double dt, int64_t nsteps) {
+  return advance(L, f, u, n_u_slices, tau_p, kappa, dt, nsteps, false);
 }
 
 static int read_flag(lattice_t* L) {
@@ -322,6 +335,40 @@ int lattice_density(lattice_t* L, const void* f, double dt, double* rho) {
   const double dvd = d.dim == 1 ? dv : dv * dv;
   HIPCHK(L, lat::launch_density(f, L->sites, (int)L->nplanes,
                                 d.dtype == LATTICE_F64, dvd, rho, L->stream));
+  return LATTICE_OK;
+}
+
+int lattice_rho_r2(lattice_t* L, const double* rho, int levels, double* out) {
+  if (!L) return LATTICE_EINVAL;
+  L->msg[0] = 0;
+  const lattice_desc& d = L->d;
+  if (!rho || !out || levels < 1 || levels > lat::kRhoMaxLevels)
+    return set_err(L, LATTICE_EINVAL, "bad rho_r2 arguments");
+  const int64_t tile = (int64_t)1 << (levels - 1);
+  if (d.nx % tile != 0 || (d.dim == 2 && d.ny % tile != 0))
+    return set_err(L, LATTICE_EINVAL,
+                   "nx (and ny) must be multiples of 2^(levels-1)");
+  const int64_t npart = lat::rho_r2_partials(d.dim, d.nx, d.ny, levels);
+  double* work = nullptr;
+  if (hipMalloc(&work, sizeof(double) * (size_t)(L->sites + 2 * npart +
+                                                 levels)) != hipSuccess)
+    return set_err(L, LATTICE_ENOMEM, "rho_r2 workspace");
+  double* partial = work + L->sites;
+  double* dout = partial + 2 * npart;
+  hipError_t e = lat::launch_rho_r2(rho, d.dim, d.nx, d.ny, levels, work,
+                                    partial, dout, L->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(out, dout, sizeof(double) * levels,
+                       hipMemcpyDeviceToHost, L->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  (void)hipFree(work);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return set_err(L, LATTICE_EHIP, hipGetErrorString(e));
+  }
+  for (int k = 0; k < levels; ++k)
+    if (!isfinite(out[k]))
+      return set_err(L, LATTICE_ENONFINITE, "rho_r2 not finite");
   return LATTICE_OK;
 }
 

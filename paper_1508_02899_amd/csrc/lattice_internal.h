@@ -53,6 +53,12 @@ hipError_t launch_moments(const void* f, int64_t sites, int nv, int dim,
                           int f64, double w, double dv, double* plane_sums,
                           double* out, hipStream_t s);
 // rho[site] = dvd * sum_j f[j][site] in FP64.
+// <rho_r^2> on tilings r = 2^k sites, k = 0..levels-1 (observables.hip).
+constexpr int kRhoMaxLevels = 32;
+int64_t rho_r2_partials(int dim, int64_t nx, int64_t ny, int levels);
+hipError_t launch_rho_r2(const double* rho, int dim, int64_t nx, int64_t ny,
+                         int levels, double* work, double* partial,
+                         double* out, hipStream_t s);
 hipError_t launch_density(const void* f, int64_t sites, int nplanes, int f64,
                           double dvd, double* rho, hipStream_t s);
 

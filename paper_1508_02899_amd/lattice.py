@@ -25,8 +25,9 @@ OK, EINVAL, ECFL, EDIFF, EHIP, ENOMEM, ENONFINITE, ENOTSUP = (
 # every symbol declared in include/lattice.h
 EXPORTS = (
     "lattice_desc_default", "lattice_velocity", "lattice_init", "lattice_step",
+    "lattice_collide",
     "lattice_moments", "lattice_density", "lattice_stability",
-    "lattice_copy_state", "lattice_sync", "lattice_profile",
+    "lattice_copy_state", "lattice_sync", "lattice_profile", "lattice_rho_r2",
     "lattice_profile_read", "lattice_destroy", "lattice_strerror",
     "lattice_last_error", "lattice_batch_init", "lattice_batch_layout",
     "lattice_batch_tune", "lattice_batch_step", "lattice_batch_moments",
@@ -110,11 +111,13 @@ def load_library(path: str = LIB_PATH):
                                    ctypes.POINTER(dbl)]
     L.lattice_init.argtypes = [pdesc, ctypes.POINTER(vp)]
     L.lattice_step.argtypes = [vp, vp, vp, i64, dbl, dbl, dbl, i64]
+    L.lattice_collide.argtypes = [vp, vp, vp, i64, dbl, dbl, dbl, i64]
     L.lattice_moments.argtypes = [vp, vp, dbl, ctypes.POINTER(Moments)]
     L.lattice_density.argtypes = [vp, vp, dbl, vp]
     L.lattice_stability.argtypes = [vp, vp, i64, dbl, dbl, dbl,
                                     ctypes.POINTER(dbl)]
     L.lattice_copy_state.argtypes = [vp, vp, vp]
+    L.lattice_rho_r2.argtypes = [vp, vp, i32, ctypes.POINTER(dbl)]
     L.lattice_sync.argtypes = [vp]
     L.lattice_profile.argtypes = [vp, i32]
     L.lattice_profile_read.argtypes = [vp, ctypes.POINTER(dbl),
@@ -144,8 +147,8 @@ def load_library(path: str = LIB_PATH):
     L.lattice_mlp_create.argtypes = [vp, ctypes.POINTER(vp)]
     L.lattice_mlp_set_params.argtypes = [vp, pf]
     L.lattice_mlp_get_params.argtypes = [vp, pf]
-    L.lattice_mlp_samples.argtypes = [vp, dbl, dbl, dbl, vp, vp, vp, vp, i64,
-                                      vp, vp, vp]
+    L.lattice_mlp_samples.argtypes = [vp, dbl, dbl, dbl, dbl, vp, vp, vp, vp,
+                                      i64, vp, vp, vp]
     L.lattice_mlp_grad.argtypes = [vp, vp, vp, vp, i64, vp,
                                    ctypes.POINTER(dbl)]
     L.lattice_mlp_train.argtypes = [vp, vp, vp, vp, i64, i64, i64, dbl,
@@ -259,15 +262,25 @@ class Lattice:
 
         u holds one or more slices ([slices, dim, ny, nx] or
         [slices, 1, nx] in 1D)."""
+        return self._advance(self.lib.lattice_step, f, u, tau_p, kappa, dt,
+                             nsteps, check)
+
+    def collide(self, f, u, tau_p: float, kappa: float, dt: float,
+                nsteps: int = 1, check: bool = True):
+        """The collision part of step() alone (no streaming, no learned
+        correction)."""
+        return self._advance(self.lib.lattice_collide, f, u, tau_p, kappa, dt,
+                             nsteps, check)
+
+    def _advance(self, fn, f, u, tau_p, kappa, dt, nsteps, check):
         s = self.spec
         fp = self._tensor_ptr(f, s.state_shape, "f")
         per = s.dim * s.nx * (s.ny if s.dim == 2 else 1)
         if u.numel() % per:
             raise ValueError("u is not a whole number of slices")
         up = self._tensor_ptr(u, None, "u")
-        rc = self.lib.lattice_step(self._L, fp, up, u.numel() // per,
-                                   float(tau_p), float(kappa), float(dt),
-                                   int(nsteps))
+        rc = fn(self._L, fp, up, u.numel() // per, float(tau_p), float(kappa),
+                float(dt), int(nsteps))
         if check:
             self._check(rc)
         return rc
@@ -299,6 +312,19 @@ class Lattice:
             self._L, self._tensor_ptr(f, None, "f"), float(dt),
             ctypes.c_void_p(rho.data_ptr())))
         return rho
+
+    def rho_r2(self, rho, levels: int):
+        """<rho_r^2> on tilings r = 2^k sites, k < levels (numpy array),
+        from an FP64 density tensor such as density() returns."""
+        import numpy as np
+        assert rho.dtype == _torch().float64 and rho.is_cuda
+        assert rho.is_contiguous() and rho.numel() == self.spec.nx * (
+            self.spec.ny if self.spec.dim == 2 else 1)
+        out = np.empty(levels, dtype=np.float64)
+        self._check(self.lib.lattice_rho_r2(
+            self._L, ctypes.c_void_p(rho.data_ptr()), int(levels),
+            out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
 
     def stability(self, u, tau_p: float, kappa: float, dt: float):
         """(CFL of Eq. 3, kappa dt_s / dv^2 of Eq. 4) for the slices in u."""
@@ -547,8 +573,10 @@ class Mlp:
         self._check(self.lib.lattice_mlp_forward(self._M, _ptr(X), n, _ptr(y)))
         return y
 
-    def samples(self, lat, dt, tau_p, St, f_pred, f_true, u, sites):
-        """Training samples at the given sites (int32 CUDA tensor)."""
+    def samples(self, lat, dt, tau_p, St, f_pred, f_true, u, sites,
+                rel_eps: float = 0.0):
+        """Training samples at the given sites (int32 CUDA tensor); faces
+        with stencil mass below rel_eps x site mass get zero weight."""
         torch = _torch()
         nf = 544
         n = sites.numel() * nf
@@ -556,7 +584,8 @@ class Mlp:
         t = torch.empty(n, dtype=torch.float32, device=f_pred.device)
         w = torch.empty(n, dtype=torch.float32, device=f_pred.device)
         self._check(self.lib.lattice_mlp_samples(
-            lat._L, float(dt), float(tau_p), float(St), _ptr(f_pred),
+            lat._L, float(dt), float(tau_p), float(St), float(rel_eps),
+            _ptr(f_pred),
             _ptr(f_true), _ptr(u), _ptr(sites), sites.numel(), _ptr(X),
             _ptr(t), _ptr(w)))
         return X, t, w
