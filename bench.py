@@ -46,6 +46,11 @@ WORKLOADS = {
     # every 50 steps, FP32, batched persistent kernels replayed as a graph
     "batch-256x1d": dict(dim=1, n=0, nv=0, s=1, dtype="f32", St=0.0,
                          kappa=1e-4, vmax=0.0, batch=256),
+    # 2D 256^2 sites: fine 65^2 velocities vs the stride-4 coarse 17^2
+    # lattice with the learned face-flux correction (trained before timing
+    # on samples of a fine run under another flow realization), St = 2
+    "coarse-mlp-256x256": dict(dim=2, n=256, nv=65, s=1, dtype="f32", St=2.0,
+                               kappa=1e-4, vmax=3.0, coarse=True),
 }
 KERNEL_SOURCES = ["paper_1508_02899_amd/csrc/step2d.h",
                   "paper_1508_02899_amd/csrc/step1d.hip",
@@ -198,6 +203,120 @@ def bench_batch(args, w):
     print(json.dumps(out), flush=True)
 
 
+def bench_coarse(args, w):
+    """Fine lattice vs coarse lattice + learned correction: per-step times,
+    the moment errors of a side-by-side run, the correction kernel's rate."""
+    import torch
+
+    from paper_1508_02899_amd import Lattice, LatticeSpec, Mlp, inputs
+    from paper_1508_02899_amd import coarse as CC
+    K, W = args.steps, args.warmup
+    L, dx, dv, dt, tau_p = geometry(w)
+    n, nvf, St, kappa = w["n"], w["nv"], w["St"], w["kappa"]
+    T_spin, T_train, T_eval = 60, 100, 200
+
+    def flow(seed, nsl):
+        u = torch.from_numpy(inputs.flow2d_streamfunction(
+            n, L, nsl, kmax=32, tau_f=1.0, dt=dt, seed=seed)).cuda()
+        fn = lambda k: u[k:k + 1]  # noqa: E731
+        fn.all = u
+        return fn
+
+    flow_a = flow(inputs.seed_for(5, 1), T_spin + T_train)
+    flow_b = flow(inputs.seed_for(5, 2), max(T_eval, W + K))
+    fs = LatticeSpec(dim=2, nx=n, ny=n, nv=nvf, dx=dx)
+    nsf = max(CC.nsub_for(fs, f.all, tau_p, kappa, dt) for f in (flow_a, flow_b))
+    fs = LatticeSpec(dim=2, nx=n, ny=n, nv=nvf, dx=dx, nsub=nsf)
+    cs = CC.coarse_spec(fs)
+    nsc = max(CC.nsub_for(cs, f.all, tau_p, kappa, dt) for f in (flow_a, flow_b))
+    cs = CC.coarse_spec(fs, nsc)
+    log(f"bench: coarse workload, fine nsub {nsf}, coarse nsub {nsc}")
+    fine, coarse, mlp = Lattice(fs), Lattice(cs), Mlp()
+    mlp.set_params(CC.initial_params(5))
+    f = torch.from_numpy(inputs.gaussian_ic(2, n, nvf, dx, dv, ny=n)).cuda()
+    for k in range(T_spin):
+        fine.step(f, flow_a(k), tau_p, kappa, dt, 1)
+    X, t, wt = CC.collect_samples(fine, coarse, mlp, f, flow_a, steps=T_train,
+                                  dt=dt, tau_p=tau_p, kappa=kappa, St=St,
+                                  sites_per_step=768, seed=1,
+                                  first_step=T_spin)
+    for lr in (3e-3, 1e-3, 3e-4):
+        loss = mlp.train(X, t, wt, batch=8192, steps=9000, lr=lr)
+    del X, t, wt
+    log(f"bench: network trained, last minibatch loss {loss:.3e}")
+
+    plain, corr = Lattice(cs), Lattice(cs)
+    mlp.attach(corr, St, 1e-3)
+    f0 = torch.from_numpy(inputs.gaussian_ic(2, n, nvf, dx, dv, ny=n)).cuda()
+    tracks, ff, states = CC.compare(fine, {"plain": plain, "mlp": corr}, f0,
+                                    flow_b, steps=T_eval, dt=dt, tau_p=tau_p,
+                                    kappa=kappa, levels=int(math.log2(n)) + 1,
+                                    every=25)
+    err_r = CC.errors({k: v for k, v in tracks.items() if k != "fine"},
+                      "fine_R", dx, from_step=50)
+    err_f = CC.errors(tracks, "fine", dx, from_step=50)
+
+    def timed(lat, state):
+        lat.step(state, flow_b(0), tau_p, kappa, dt, W) if W else None
+        lat.sync()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for k in range(K):
+            lat.step(state, flow_b(W + k), tau_p, kappa, dt, 1)
+        e1.record()
+        torch.cuda.synchronize()
+        lat.sync()
+        return e0.elapsed_time(e1) / K
+
+    ms_fine = timed(fine, ff)
+    ms_plain = timed(plain, states["plain"])
+    ms_mlp = timed(corr, states["mlp"])
+    # correction kernel on every face (no line skipped): nominal flops
+    full = Lattice(cs)
+    mlp.attach(full, St, 0.0)
+    ms_full = timed(full, states["plain"].clone())
+    t_corr = max(ms_full - ms_plain, 1e-9) / 1e3
+    flops = 2 * n * n * 17 * 16 * (2 * 8 * 64 + 2 * 64 * 64 + 2 * 64) + 0.0
+    achieved = flops / t_corr / 1e12
+    cells_f = n * n * nvf * nvf
+    value = cells_f / (ms_mlp / 1e3) / 1e9
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "GCUPS",
+        "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": round(ms_mlp, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"coarse-mlp-256x256: 2D periodic 256^2 sites; fine "
+                         f"{nvf}^2 velocities (nsub {nsf}) vs stride-4 coarse "
+                         f"17^2 (nsub {nsc}) + learned face-flux correction "
+                         "(8-64-64-1 GELU, bf16 matrix cores, lines below "
+                         f"1e-3 of the site mass skipped), St={St}, "
+                         f"kappa={kappa}, Vmax={w['vmax']} u_rms, koren; value"
+                         " = fine-lattice cell updates per second delivered "
+                         "by the coarse model"),
+            "ms_per_step_fine": round(ms_fine, 5),
+            "ms_per_step_coarse_plain": round(ms_plain, 5),
+            "ms_per_step_coarse_mlp": round(ms_mlp, 5),
+            "speedup_vs_fine": round(ms_fine / ms_mlp, 3),
+            "errors_vs_restricted_fine": err_r,
+            "errors_vs_fine": err_f,
+        },
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 2),
+                     "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": round(achieved / 2500.0, 4), "traffic": None,
+                     "kernel": "k_mlp_correct17 (all 544 faces per site)",
+                     "flops_per_launch": flops,
+                     "avg_launch_us": round(t_corr * 1e6, 2)},
+    }
+    for lat in (fine, coarse, plain, corr, full):
+        lat.close()
+    mlp.close()
+    print(json.dumps(out), flush=True)
+
+
 def load_traffic(name):
     path = os.path.join(ROOT, "profiles", f"traffic_{name}.json")
     if not os.path.exists(path):
@@ -347,6 +466,9 @@ def main():
     if w.get("batch"):
         torch.cuda.set_device(0)
         return bench_batch(args, w)
+    if w.get("coarse"):
+        torch.cuda.set_device(0)
+        return bench_coarse(args, w)
     L, dx, dv, dt, tau_p = geometry(w)
     npdt = np.float64 if w["dtype"] == "f64" else np.float32
     n, nv, dim = w["n"], w["nv"], w["dim"]
