@@ -115,3 +115,28 @@ def test_corrected_site_conserves_mass_and_positivity():
     out = C.corrected_site(fc, nv, y, ms, sg)
     assert out.sum() == pytest.approx(fc.sum(), rel=1e-13)
     assert out.min() >= -1e-15
+
+
+def test_face_features_hand_example():
+    """Hand-built 5x5 square (rows jy, columns jx), u = 0: the stencil is
+    read from the upwind side (donor first), normalised by its mass; the
+    drift feature is |nu| = dt |u - v_face| / (tau_p dv)."""
+    nv, dv, dt, tau, St = 5, 0.5, 0.2, 2.0, 3.0
+    c = np.zeros((nv, nv))
+    c[0, :] = [1, 2, 3, 4, 5]          # row jy = 0 carries the x-faces checked
+    X, ms, sg = C.face_features(c.ravel(), nv, 0.0, 0.0, dv, dt, tau, St)
+    assert X.shape == (2 * nv * (nv - 1), 8)
+    # x-face k = 2 of row 0 (index 1): v_face = -dv/2 < u -> nu > 0, donor
+    # cell 1; stencil cells (-1, 0, 1, 2, 3) = (0, 1, 2, 3, 4), mass 10
+    assert ms[1] == 10 and sg[1] == 1
+    assert np.allclose(X[1], [0, .1, .2, .3, .4, 0.5 * dt / tau, np.log(St), 0])
+    # x-face k = 3 (index 2): v_face = +dv/2 -> nu < 0, donor cell 3;
+    # stencil cells (5, 4, 3, 2, 1) = (0, 5, 4, 3, 2), mass 14
+    assert ms[2] == 14 and sg[2] == -1
+    assert np.allclose(X[2, :5], np.array([0, 5, 4, 3, 2]) / 14)
+    assert X[2, 5] == pytest.approx(0.5 * dt / tau)
+    # y-faces of an empty column carry no mass and zero stencil features
+    ny0 = nv * (nv - 1)
+    assert ms[ny0 + 1 * nv + 4] > 0      # column 4: row 0 holds 5
+    assert ms[ny0 + 3 * nv + 4] == 0     # face 4 of column 4: cells 1..4 empty
+    assert np.all(X[ny0 + 3 * nv + 4, :5] == 0)
