@@ -192,6 +192,30 @@ int lattice_density(lattice_t* L, const void* f, double dt, double* rho);
 int lattice_rho_r2(lattice_t* L, const double* rho, int levels, double* out);
 
 /*
+ * Carrier-flow synthesis on the device from Fourier mode tables (the random
+ * Fourier flows of Sec. 3 and the streamfunction flows of Sec. 4; Eq. 7
+ * gives the Ornstein-Uhlenbeck time law of the amplitudes, which the host
+ * draws): the mode amplitudes of n_slices time slices in, u slices in the
+ * layout lattice_step reads out.  Asynchronous on the handle's stream.
+ *
+ * 1D (dim 1): coef = device FP32 [n_slices][nmodes][2] = (a_k, b_k) for
+ *   k = 1..nmodes; u[s][0][ix] = sum_k a_k cos(2 pi k ix/nx)
+ *   + b_k sin(2 pi k ix/nx) in the lattice dtype.  EINVAL.
+ * 2D (dim 2): coef = device FP32 [n_slices][2 kmax + 1][kmax + 1][2], the
+ *   complex streamfunction amplitudes c(ky, kx) for ky = -kmax..kmax (row
+ *   ky + kmax), kx = 0..kmax; psi(ix, iy) = sum Re(c e^{2 pi i (kx ix/nx +
+ *   ky iy/ny)}), u[s][0] = d psi/dy, u[s][1] = -d psi/dx with the site
+ *   spacing dx of the lattice (domain nx dx by ny dx).  Two separable passes
+ *   (along x, then along y) through a stream-ordered temporary of
+ *   2 (2 kmax + 1) nx n_slices complex values.  1 <= kmax <= 64,
+ *   2 kmax < nx, ny; n_slices, ny <= 65535.  EINVAL, EHIP.
+ */
+int lattice_flow1d_modes(lattice_t* L, int32_t nmodes, const float* coef,
+                         int64_t n_slices, void* u);
+int lattice_flow2d_modes(lattice_t* L, int32_t kmax, const float* coef,
+                         int64_t n_slices, void* u);
+
+/*
  * Largest drift CFL number of Eq. 3 and the diffusion number of Eq. 4 for
  * the given u slices (device) and parameters: out[0] = (dt_s/dv)
  * (max|u_k| + Vmax)/tau_p, out[1] = kappa dt_s/dv^2 (out host, 2 doubles).

@@ -76,11 +76,11 @@ def _mode_sigmas(kmodes: np.ndarray, spectrum: str) -> np.ndarray:
     return s / np.sqrt(np.sum(s * s))
 
 
-def flow1d(nx: int, L: float, nslices: int, *, modes: int = 8,
-           spectrum: str = "k-1", urms: float = 1.0, renew: int | None = None,
-           tau_f: float | None = None, dt: float = 1.0, seed: int = 0,
-           dtype=np.float32):
-    """u[slice, 1, nx] for a 1D random Fourier flow.
+def flow1d_modes(nslices: int, *, modes: int = 8, spectrum: str = "k-1",
+                 urms: float = 1.0, renew: int | None = None,
+                 tau_f: float | None = None, dt: float = 1.0, seed: int = 0):
+    """Mode table [slice, mode, 2] (FP64) of a 1D random Fourier flow:
+    u(x) = sum_k a_k cos(2 pi k x / L) + b_k sin(2 pi k x / L), k = 1..modes.
 
     ``renew``: consecutive slices are independent draws (each slice is held
     for ``renew`` steps by the caller through u_hold).  ``tau_f``: slices
@@ -88,12 +88,9 @@ def flow1d(nx: int, L: float, nslices: int, *, modes: int = 8,
     rng = np.random.default_rng(seed)
     k = np.arange(1, modes + 1, dtype=float)
     sig = urms * _mode_sigmas(k, spectrum)
-    x = np.arange(nx) * (L / nx)
-    ph = 2.0 * np.pi * np.outer(k, x) / L  # [modes, nx]
-    C, S = np.cos(ph), np.sin(ph)
     a = sig * rng.standard_normal(modes)
     b = sig * rng.standard_normal(modes)
-    out = np.empty((nslices, 1, nx), dtype=np.float64)
+    out = np.empty((nslices, modes, 2))
     if tau_f is not None:
         rho = np.exp(-dt / tau_f)
         q = np.sqrt(1.0 - rho * rho)
@@ -105,19 +102,33 @@ def flow1d(nx: int, L: float, nslices: int, *, modes: int = 8,
             else:
                 a = sig * rng.standard_normal(modes)
                 b = sig * rng.standard_normal(modes)
-        out[s, 0] = a @ C + b @ S
+        out[s, :, 0] = a
+        out[s, :, 1] = b
+    return out
+
+
+def flow1d(nx: int, L: float, nslices: int, *, modes: int = 8,
+           spectrum: str = "k-1", urms: float = 1.0, renew: int | None = None,
+           tau_f: float | None = None, dt: float = 1.0, seed: int = 0,
+           dtype=np.float32):
+    """u[slice, 1, nx] of the flow1d_modes table (prestaged form)."""
+    tab = flow1d_modes(nslices, modes=modes, spectrum=spectrum, urms=urms,
+                       renew=renew, tau_f=tau_f, dt=dt, seed=seed)
+    k = np.arange(1, modes + 1, dtype=float)
+    x = np.arange(nx) * (L / nx)
+    ph = 2.0 * np.pi * np.outer(k, x) / L  # [modes, nx]
+    C, S = np.cos(ph), np.sin(ph)
+    out = (tab[:, :, 0] @ C + tab[:, :, 1] @ S)[:, None, :]
     return np.ascontiguousarray(out.astype(dtype))
 
 
 # ---------------------------------------------------------------------------
 # 2D incompressible flows
-def flow2d_streamfunction(n: int, L: float, nslices: int, *, kmin: int = 1,
-                          kmax: int = 32, slope: float = -3.0,
-                          urms: float = 1.0, tau_f: float = 1.0,
-                          dt: float = 1.0, seed: int = 0, dtype=np.float32):
-    """u[slice, 2, n, n] = (d_y psi, -d_x psi) for a random streamfunction
-    with energy shell spectrum E(k) ~ k^slope on kmin <= |k| <= kmax and OU
-    time evolution (correlation time tau_f) of every Fourier mode."""
+def _psi_hat_slices(n: int, nslices: int, kmin: int, kmax: int, slope: float,
+                    tau_f: float, dt: float, seed: int):
+    """Streamfunction Fourier amplitudes on the rfft grid [n, n//2+1], one
+    array per slice: energy shell spectrum E(k) ~ k^slope on kmin <= |k| <=
+    kmax, every mode an OU process in time (correlation time tau_f)."""
     rng = np.random.default_rng(seed)
     kx = np.fft.rfftfreq(n, d=1.0 / n)          # 0..n/2
     ky = np.fft.fftfreq(n, d=1.0 / n)           # 0..n/2-1, -n/2..-1
@@ -137,17 +148,74 @@ def flow2d_streamfunction(n: int, L: float, nslices: int, *, kmin: int = 1,
     psi_hat = draw()
     rho = np.exp(-dt / tau_f)
     q = np.sqrt(1.0 - rho * rho)
-    k2pi = 2.0 * np.pi / L
-    out = np.empty((nslices, 2, n, n), dtype=np.float64)
     for s in range(nslices):
         if s > 0:
             psi_hat = rho * psi_hat + q * draw()
-        ux = np.fft.irfft2(1j * KY * k2pi * psi_hat, s=(n, n))
-        uy = np.fft.irfft2(-1j * KX * k2pi * psi_hat, s=(n, n))
-        out[s, 0] = ux
-        out[s, 1] = uy
+        yield KX, KY, psi_hat
+
+
+def _mean_square(A):
+    """Grid mean of f = sum Re(A e^{i theta}) over a table with kx >= 0
+    (rows ky = -K..K, columns kx = 0..K), by Parseval: kx >= 1 modes give
+    |A|^2 / 2; the kx = 0 column pairs (ky, -ky) give |A_ky + conj A_-ky|^2
+    / 2 for ky > 0."""
+    K = A.shape[1] - 1
+    ms = 0.5 * np.sum(np.abs(A[:, 1:]) ** 2)
+    col = A[:, 0]
+    for ky in range(1, K + 1):
+        ms += 0.5 * abs(col[K + ky] + np.conj(col[K - ky])) ** 2
+    return ms
+
+
+def flow2d_modes(n: int, L: float, nslices: int, *, kmin: int = 1,
+                 kmax: int = 32, slope: float = -3.0, urms: float = 1.0,
+                 tau_f: float = 1.0, dt: float = 1.0, seed: int = 0):
+    """Streamfunction mode table c[slice, ky + kmax, kx, 2] (FP32, re/im;
+    ky = -kmax..kmax, kx = 0..kmax) with psi(ix, iy) = sum Re(c
+    e^{2 pi i (kx ix + ky iy)/n}); u = (d_y psi, -d_x psi) has per-component
+    r.m.s. urms over all slices.  Same random draws as
+    flow2d_streamfunction (which evaluates this table on the grid)."""
+    K = kmax
+    assert 2 * K < n
+    tab = np.empty((nslices, 2 * K + 1, K + 1), dtype=np.complex128)
+    rows = np.r_[np.arange(n - K, n), np.arange(0, K + 1)]  # ky = -K..K
+    w = np.full(K + 1, 2.0)
+    w[0] = 1.0  # the kx = 0 column is counted once (real part)
+    k2pi = 2.0 * np.pi / L
+    kxv = np.arange(K + 1, dtype=float)
+    kyv = np.arange(-K, K + 1, dtype=float)
+    msum = 0.0
+    for s, (_, _, ph) in enumerate(_psi_hat_slices(n, nslices, kmin, kmax,
+                                                   slope, tau_f, dt, seed)):
+        c = ph[rows][:, :K + 1] * (w / (n * n))
+        tab[s] = c
+        ax = 1j * k2pi * kyv[:, None] * c
+        ay = -1j * k2pi * kxv[None, :] * c
+        msum += 0.5 * (_mean_square(ax) + _mean_square(ay))
+    r = np.sqrt(msum / nslices)
+    tab *= urms / r
+    out = np.empty(tab.shape + (2,), dtype=np.float32)
+    out[..., 0] = tab.real
+    out[..., 1] = tab.imag
+    return out
+
+
+def flow2d_streamfunction(n: int, L: float, nslices: int, *, kmin: int = 1,
+                          kmax: int = 32, slope: float = -3.0,
+                          urms: float = 1.0, tau_f: float = 1.0,
+                          dt: float = 1.0, seed: int = 0, dtype=np.float32):
+    """u[slice, 2, n, n] = (d_y psi, -d_x psi) for a random streamfunction
+    with energy shell spectrum E(k) ~ k^slope on kmin <= |k| <= kmax and OU
+    time evolution (correlation time tau_f) of every Fourier mode
+    (prestaged form of flow2d_modes, evaluated with inverse real FFTs)."""
+    k2pi = 2.0 * np.pi / L
+    out = np.empty((nslices, 2, n, n), dtype=np.float64)
+    for s, (KX, KY, psi_hat) in enumerate(_psi_hat_slices(
+            n, nslices, kmin, kmax, slope, tau_f, dt, seed)):
+        out[s, 0] = np.fft.irfft2(1j * KY * k2pi * psi_hat, s=(n, n))
+        out[s, 1] = np.fft.irfft2(-1j * KX * k2pi * psi_hat, s=(n, n))
     # ensemble normalisation: the stationary per-component variance is the
-    # same for every slice; scale by the measured r.m.s. over all slices
+    # same for every slice; scale by the r.m.s. over all slices
     r = np.sqrt(0.5 * (np.mean(out[:, 0] ** 2) + np.mean(out[:, 1] ** 2)))
     out *= urms / r
     return np.ascontiguousarray(out.astype(dtype))

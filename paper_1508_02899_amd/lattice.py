@@ -28,6 +28,7 @@ EXPORTS = (
     "lattice_collide",
     "lattice_moments", "lattice_density", "lattice_stability",
     "lattice_copy_state", "lattice_sync", "lattice_profile", "lattice_rho_r2",
+    "lattice_flow1d_modes", "lattice_flow2d_modes",
     "lattice_profile_read", "lattice_destroy", "lattice_strerror",
     "lattice_last_error", "lattice_batch_init", "lattice_batch_layout",
     "lattice_batch_tune", "lattice_batch_step", "lattice_batch_moments",
@@ -118,6 +119,8 @@ def load_library(path: str = LIB_PATH):
                                     ctypes.POINTER(dbl)]
     L.lattice_copy_state.argtypes = [vp, vp, vp]
     L.lattice_rho_r2.argtypes = [vp, vp, i32, ctypes.POINTER(dbl)]
+    L.lattice_flow1d_modes.argtypes = [vp, i32, vp, i64, vp]
+    L.lattice_flow2d_modes.argtypes = [vp, i32, vp, i64, vp]
     L.lattice_sync.argtypes = [vp]
     L.lattice_profile.argtypes = [vp, i32]
     L.lattice_profile_read.argtypes = [vp, ctypes.POINTER(dbl),
@@ -312,6 +315,32 @@ class Lattice:
             self._L, self._tensor_ptr(f, None, "f"), float(dt),
             ctypes.c_void_p(rho.data_ptr())))
         return rho
+
+    def flow_from_modes(self, coef, out=None):
+        """u slices synthesised on the device from a mode table (FP32 CUDA
+        tensor): 1D [slices, K, 2] (a_k, b_k); 2D [slices, 2K+1, K+1, 2]
+        (streamfunction amplitudes).  Returns [slices, dim, ny, nx] (2D) or
+        [slices, 1, nx] (1D) in the lattice dtype."""
+        torch = _torch()
+        s = self.spec
+        assert coef.dtype == torch.float32 and coef.is_cuda
+        assert coef.is_contiguous() and coef.shape[-1] == 2
+        ns = coef.shape[0]
+        dt = torch.float64 if s.dtype == "f64" else torch.float32
+        shape = (ns, 2, s.ny, s.nx) if s.dim == 2 else (ns, 1, s.nx)
+        if out is None:
+            out = torch.empty(shape, dtype=dt, device=coef.device)
+        assert tuple(out.shape) == shape and out.dtype == dt
+        if s.dim == 1:
+            rc = self.lib.lattice_flow1d_modes(self._L, coef.shape[1],
+                                               _ptr(coef), ns, _ptr(out))
+        else:
+            K = coef.shape[2] - 1
+            assert coef.shape[1] == 2 * K + 1
+            rc = self.lib.lattice_flow2d_modes(self._L, K, _ptr(coef), ns,
+                                               _ptr(out))
+        self._check(rc)
+        return out
 
     def rho_r2(self, rho, levels: int):
         """<rho_r^2> on tilings r = 2^k sites, k < levels (numpy array),
