@@ -192,6 +192,22 @@ int lattice_density(lattice_t* L, const void* f, double dt, double* rho);
 int lattice_rho_r2(lattice_t* L, const double* rho, int levels, double* out);
 
 /*
+ * Eulerian first-order structure function of the particle velocity (Eq. 11,
+ * Sec. 3.1; its scaling exponent is studied in Secs. 3.2 and 4.2.1):
+ *   S1(r) = <sum_{j,j'} f(x,v_j) f(x+r,v_j') |v_j - v_j'|>_x
+ *           / <sum_{j,j'} f(x,v_j) f(x+r,v_j')>_x
+ * for the nr separations r[k] (host, int32, in lattice sites, >= 0;
+ * periodic).  1D: r along x.  2D: |v - v'| is the Euclidean distance on the
+ * velocity square; the estimate is the mean of the separations r e_x and
+ * r e_y.  out: host, nr doubles.  FP64 correlation sums in a fixed order;
+ * in 2D the velocity-space product runs as one GEMM (rocBLAS) in the state
+ * dtype.  Synchronous; allocates a temporary device workspace of one state
+ * plus (2D) an nv^2 x nv^2 matrix.  EINVAL, ENOMEM, ENONFINITE, EHIP.
+ */
+int lattice_s1(lattice_t* L, const void* f, double dt, int32_t nr,
+               const int32_t* r, double* out);
+
+/*
  * Carrier-flow synthesis on the device from Fourier mode tables (the random
  * Fourier flows of Sec. 3 and the streamfunction flows of Sec. 4; Eq. 7
  * gives the Ornstein-Uhlenbeck time law of the amplitudes, which the host

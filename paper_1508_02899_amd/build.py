@@ -38,8 +38,9 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = SO + ".tmp"
+    # rocBLAS: the plain GEMM of the 2D structure function (s1.hip)
     subprocess.check_call(["hipcc", f"--offload-arch={ARCH}", "-shared",
-                           "-fPIC", "-o", tmp, *objs])
+                           "-fPIC", "-o", tmp, *objs, "-lrocblas"])
     os.replace(tmp, SO)
     if verbose:
         print("built", SO)

@@ -28,7 +28,7 @@ EXPORTS = (
     "lattice_collide",
     "lattice_moments", "lattice_density", "lattice_stability",
     "lattice_copy_state", "lattice_sync", "lattice_profile", "lattice_rho_r2",
-    "lattice_flow1d_modes", "lattice_flow2d_modes",
+    "lattice_flow1d_modes", "lattice_flow2d_modes", "lattice_s1",
     "lattice_profile_read", "lattice_destroy", "lattice_strerror",
     "lattice_last_error", "lattice_batch_init", "lattice_batch_layout",
     "lattice_batch_tune", "lattice_batch_step", "lattice_batch_moments",
@@ -120,6 +120,8 @@ def load_library(path: str = LIB_PATH):
     L.lattice_copy_state.argtypes = [vp, vp, vp]
     L.lattice_rho_r2.argtypes = [vp, vp, i32, ctypes.POINTER(dbl)]
     L.lattice_flow1d_modes.argtypes = [vp, i32, vp, i64, vp]
+    L.lattice_s1.argtypes = [vp, vp, dbl, i32, ctypes.POINTER(i32),
+                             ctypes.POINTER(dbl)]
     L.lattice_flow2d_modes.argtypes = [vp, i32, vp, i64, vp]
     L.lattice_sync.argtypes = [vp]
     L.lattice_profile.argtypes = [vp, i32]
@@ -340,6 +342,18 @@ class Lattice:
             rc = self.lib.lattice_flow2d_modes(self._L, K, _ptr(coef), ns,
                                                _ptr(out))
         self._check(rc)
+        return out
+
+    def s1(self, f, dt: float, r):
+        """S1(r) of Eq. 11 for separations r (sites) as a numpy array."""
+        import numpy as np
+        rr = np.ascontiguousarray(np.asarray(r, dtype=np.int32))
+        out = np.empty(rr.size, dtype=np.float64)
+        self._check(self.lib.lattice_s1(
+            self._L, self._tensor_ptr(f, self.spec.state_shape, "f"),
+            float(dt), int(rr.size),
+            rr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+            out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return out
 
     def rho_r2(self, rho, levels: int):
