@@ -193,16 +193,17 @@ struct Step2D {
   }
 };
 
-// Output staging of a workgroup (P > 1).  The 4 wavefronts of a workgroup
-// own G = 4S consecutive sites of one spatial row; a wavefront's direct
-// stores would write S-site pieces of P planes per instruction.  Instead
-// each finished row goes to LDS and the workgroup stores it plane by plane,
-// 64 consecutive elements per store instruction.  The plane stride is
+// Output staging of a workgroup (P > 1).  The WGW wavefronts of a
+// workgroup own G = WGW S consecutive sites of one spatial row; a
+// wavefront's direct stores would write S-site pieces of P planes per
+// instruction.  Instead each finished row goes to LDS and the workgroup
+// stores it plane by plane, 64 consecutive elements per store instruction
+// (and G consecutive elements per plane per round).  The plane stride is
 // padded so that the P parts of a wavefront write to disjoint LDS banks.
-template <typename T, int NV, int P>
+template <typename T, int NV, int P, int WGW>
 struct OutStage {
   static constexpr int S = 64 / P;
-  static constexpr int G = 4 * S;          // sites per workgroup
+  static constexpr int G = WGW * S;        // sites per workgroup
   static constexpr int W = (NV - 1) / P + 1;
   static constexpr int DW = sizeof(T) / 4;  // dwords per element
   static constexpr int pad() {
@@ -226,17 +227,27 @@ struct OutStage {
   static constexpr int K = (NV + P - 1) / P;    // stores per thread per row
 };
 
+// Wavefronts per workgroup: wider workgroups make each stored plane run
+// longer (measured on the row-streaming copy pattern: 128 consecutive
+// sites per workgroup beat 64) at the cost of a barrier over more waves.
+template <typename T, int NV, int P>
+constexpr int step2d_wgw() {
+  // nv = 65 (17 cells per lane) needs more than the 256 registers a wave
+  // may hold at 8 waves per workgroup
+  return (P == 4 && sizeof(T) == 4 && NV <= 33) ? 8 : 4;
+}
+
 // INTERIOR: every source site of the tile lies inside [0, nx) without
 // wrapping, so all cells of a row load from one uniform base plus one
 // per-lane offset (plus a uniform per-cell stride); otherwise each cell
 // keeps its own wrapped offset.
-template <typename T, int NV, int P, bool KOREN, bool INTERIOR>
+template <typename T, int NV, int P, bool KOREN, bool INTERIOR, int WGW>
 __device__ __forceinline__ void step2d_tile(
     const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict__ u,
     T* __restrict__ stage, int nx, int ny, int shift, int xstep, int xoff0,
     int ystep, int yoff0, T alpha_scale, T beta, T D, int xg, int w, int y) {
   using K = Step2D<T, NV, P, KOREN>;
-  using O = OutStage<T, NV, P>;
+  using O = OutStage<T, NV, P, WGW>;
   constexpr int W = K::W, S = K::S, H = K::H, G = O::G;
   const int lane = (int)threadIdx.x & 63;
   const int p = lane / S;
@@ -415,17 +426,18 @@ __device__ __forceinline__ void step2d_tile(
   run_row(edge_t(), NV + 2, bufB, s1, s0);
 }
 
-// One workgroup = 4 wavefronts = G consecutive sites of spatial row y.  All
-// four run the same row sequence (the staged stores synchronise them once
+// One workgroup = WGW wavefronts = G consecutive sites of spatial row y.  All
+// run the same row sequence (the staged stores synchronise them once
 // per row), so none may leave early; wavefronts past the end of the row
 // compute on duplicated sites and store nothing.
-template <typename T, int NV, int P, bool KOREN>
-__global__ __launch_bounds__(256) void k_step2d(
+template <typename T, int NV, int P, bool KOREN,
+          int WGW = step2d_wgw<T, NV, P>()>
+__global__ __launch_bounds__(64 * WGW) void k_step2d(
     const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict__ u,
     const int* __restrict__ flag, int nx, int ny, int shift, int xstep,
     int xoff0, int ystep, int yoff0, T alpha_scale, T beta, T D, int ngx,
     int nblocks) {
-  using O = OutStage<T, NV, P>;
+  using O = OutStage<T, NV, P, WGW>;
   constexpr int S = 64 / P;
   constexpr int H = (NV - 1) / 2;
   __shared__ T stage[P > 1 ? 2 * O::SIZE : 1];
@@ -438,18 +450,19 @@ __global__ __launch_bounds__(256) void k_step2d(
   const bool interior = x0 + S <= nx && x0 - shift * H >= 0 &&
                         x0 + S - 1 + shift * H <= nx - 1;
   if (interior)
-    step2d_tile<T, NV, P, KOREN, true>(fin, fout, u, stage, nx, ny, shift,
+    step2d_tile<T, NV, P, KOREN, true, WGW>(fin, fout, u, stage, nx, ny, shift,
                                        xstep, xoff0, ystep, yoff0,
                                        alpha_scale, beta, D, xg, w, y);
   else
-    step2d_tile<T, NV, P, KOREN, false>(fin, fout, u, stage, nx, ny, shift,
+    step2d_tile<T, NV, P, KOREN, false, WGW>(fin, fout, u, stage, nx, ny, shift,
                                         xstep, xoff0, ystep, yoff0,
                                         alpha_scale, beta, D, xg, w, y);
 }
 
 template <typename T, int NV, int P>
 hipError_t launch_step2d_nv(const StepArgs& a, hipStream_t s) {
-  constexpr int G = OutStage<T, NV, P>::G;
+  constexpr int WGW = step2d_wgw<T, NV, P>();
+  constexpr int G = OutStage<T, NV, P, WGW>::G;
   if (!step2d_offsets_fit(NV, a.nx, a.ny, sizeof(T)))
     return hipErrorNotSupported;
   const int nx = (int)a.nx, ny = (int)a.ny;
@@ -464,12 +477,14 @@ hipError_t launch_step2d_nv(const StepArgs& a, hipStream_t s) {
   const int yoff0 = (int)(((int64_t)a.shift * H) % ny);
   const T as = (T)a.alpha_scale, be = (T)a.beta, D = (T)a.D;
   if (a.koren)
-    hipLaunchKernelGGL((k_step2d<T, NV, P, true>), dim3(nblocks), dim3(256), 0,
+    hipLaunchKernelGGL((k_step2d<T, NV, P, true>), dim3(nblocks),
+                       dim3(64 * WGW), 0,
                        s, (const T*)a.fin, (T*)a.fout, (const T*)a.u, a.flag,
                        nx, ny, a.shift, xstep, xoff0, ystep, yoff0, as, be, D,
                        ngx, nblocks);
   else
-    hipLaunchKernelGGL((k_step2d<T, NV, P, false>), dim3(nblocks), dim3(256),
+    hipLaunchKernelGGL((k_step2d<T, NV, P, false>), dim3(nblocks),
+                       dim3(64 * WGW),
                        0, s, (const T*)a.fin, (T*)a.fout, (const T*)a.u,
                        a.flag, nx, ny, a.shift, xstep, xoff0, ystep, yoff0, as,
                        be, D, ngx, nblocks);
