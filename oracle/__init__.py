@@ -21,7 +21,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
-_SO = os.path.join(_HERE, "liboracle.so")
+# ORACLE_LIB names another build of oracle.c to load instead (used by the
+# mutation test, which checks that the pins catch planted mistakes)
+_SO = os.environ.get("ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 
 SCHEMES = {"upwind": 0, "koren": 1}
 
