@@ -308,3 +308,77 @@ def test_2d_512x512_v33_full_size_sampled_sites():
     say("  worst site rel L2", worst)
     assert worst <= FP32_REL_L2
     lat.close()
+
+
+def test_1d_16384x129_full_size_full_state():
+    """1D 16384 x 129 FP32 (configuration 2 shape: 32 OU modes with k^-5/3
+    variance, St = 1, Vmax = 2, kappa = 1e-4, one flow slice per step,
+    Koren), 6 steps on the GPU against the oracle over the whole state."""
+    import torch
+    from paper_1508_02899_amd import Lattice, LatticeSpec, inputs
+    say("config-2 full size parity")
+    n, nv, L, steps = 16384, 129, 2 * math.pi, 6
+    h = (nv - 1) // 2
+    dx = L / n
+    dv = 2.0 / h
+    dt = dx / dv
+    tau_p = 2 * math.pi
+    u = inputs.flow1d(n, L, steps, modes=32, spectrum="k-5/3", tau_f=1.0,
+                      dt=dt, seed=inputs.seed_for(2))
+    f0 = inputs.gaussian_ic(1, n, nv, dx, dv)
+    p = dict(dim=1, dx=dx, dt=dt, tau_p=tau_p, kappa=1e-4, s=1, nsub=1,
+             scheme="koren", u_hold=1)
+    lat = Lattice(LatticeSpec(dim=1, nx=n, nv=nv, dx=dx, u_hold=1))
+    fd = torch.from_numpy(f0).cuda()
+    lat.step(fd, torch.from_numpy(u).cuda(), tau_p, p["kappa"], dt, steps)
+    lat.sync()
+    got = fd.cpu().numpy()
+    want = run_oracle(f0, u, p, steps, u_hold=1)
+    err = rel_l2(got, want)
+    say("  rel L2", err)
+    assert err <= FP32_REL_L2
+    lat.close()
+
+
+def test_2d_256x256_v65_full_size_sampled_sites():
+    """2D 256^2 x 65^2 FP32 (the fine lattice of configuration 5, 1.1 GB
+    state), St = 2 with 4 collision sub-steps: one step on the GPU; 40
+    sampled sites recomputed one by one by the oracle."""
+    import torch
+    import oracle
+    from paper_1508_02899_amd import Lattice, LatticeSpec, inputs
+    say("config-5 fine lattice full size sampled parity")
+    n, nv, L, nsub = 256, 65, 2 * math.pi, 4
+    h = (nv - 1) // 2
+    u = inputs.flow2d_streamfunction(n, L, 1, seed=inputs.seed_for(5))
+    dv = 3.0 / h
+    dx = L / n
+    dt = dx / dv
+    tau_p = 2 * 2 * math.pi  # St = 2
+    kappa = 1e-4
+    f0 = torch.rand((nv * nv, n, n), generator=torch.Generator().manual_seed(5),
+                    dtype=torch.float32)
+    lat = Lattice(LatticeSpec(dim=2, nx=n, ny=n, nv=nv, dx=dx, nsub=nsub))
+    ud = torch.from_numpy(u).cuda()
+    cfl, _ = lat.stability(ud, tau_p, kappa, dt)
+    assert cfl <= 0.5
+    fd = f0.cuda()
+    lat.step(fd, ud, tau_p, kappa, dt, 1)
+    lat.sync()
+    out = fd.cpu().numpy()
+    f0n = f0.numpy()
+    rng = np.random.default_rng(17)
+    sites = [(0, 0), (n - 1, n - 1), (0, n - 1), (128, 3)]
+    sites += [tuple(rng.integers(0, n, 2)) for _ in range(36)]
+    jy, jx = np.divmod(np.arange(nv * nv), nv)
+    worst = 0.0
+    for (y, x) in sites:
+        col = f0n[np.arange(nv * nv), (y - (jy - h)) % n, (x - (jx - h)) % n]
+        uu = u[:, :, y:y + 1, x:x + 1].astype(np.float64)
+        ref = oracle.step(col.reshape(nv * nv, 1, 1).astype(np.float64), uu,
+                          dim=2, dx=dx, tau_p=tau_p, kappa=kappa, dt=dt,
+                          nsteps=1, nsub=nsub)
+        worst = max(worst, rel_l2(out[:, y, x], ref[:, 0, 0]))
+    say("  worst site rel L2", worst)
+    assert worst <= FP32_REL_L2
+    lat.close()
