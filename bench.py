@@ -38,9 +38,9 @@ WORKLOADS = {
     "2d-256x256-v17s4": dict(dim=2, n=256, nv=17, s=4, dtype="f32", St=2.0,
                              kappa=1e-4, vmax=3.0),
     "1d-16384-v129": dict(dim=1, n=16384, nv=129, s=1, dtype="f32", St=1.0,
-                          kappa=1e-4, vmax=2.0),
+                          kappa=1e-4, vmax=2.0, run_steps=20000),
     "1d-256-v33-f64": dict(dim=1, n=256, nv=33, s=1, dtype="f64", St=1.0,
-                           kappa=1e-3, vmax=5.0),
+                           kappa=1e-3, vmax=5.0, run_steps=1000),
     # 256 independent 1D realizations, nx ~ U[512, 8192], nv in
     # {33, 65, 129}, St log-uniform in [0.1, 10], own 8-mode flow renewed
     # every 50 steps, FP32, batched persistent kernels replayed as a graph
@@ -108,7 +108,9 @@ def cpu_baseline(w, name, dx, dv, dt, tau_p):
         cells = m * m * w["nv"] ** 2
     else:
         m = w["n"]
-        steps = 20 if w["nv"] > 33 else 200
+        # about 10 s of oracle time (~6e7 cell updates/s), at most the
+        # workload's own run
+        steps = max(20, min(w.get("run_steps", 1000), int(6e8 / (m * w["nv"]))))
         u = make_flow(w, 1, dt, np.float32)
         f0 = inputs.gaussian_ic(1, m, w["nv"], dx, dv)
         sample = f"full {m} x {w['nv']} lattice, {steps} steps"
@@ -531,8 +533,14 @@ def main():
     if W:
         run_steps(0, W)
         lat.sync()
+    # Launch durations: HIP events around every step launch on the
+    # library's stream.  For the 2D lattices (launches of hundreds of us)
+    # they are taken inside the timed region; a 1D step lasts a few us, and
+    # per-launch events there would add their own latency to the steps, so
+    # they are taken over a second pass of the same K steps right after it.
+    inline_events = dim == 2
     torch.cuda.synchronize()
-    lat.profile(True)
+    lat.profile(inline_events)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
@@ -543,6 +551,10 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ev_ms = ev0.elapsed_time(ev1)
+    if not inline_events:
+        lat.profile(True)
+        run_steps(W, K)
+        lat.sync()
     kern_ms, launches = lat.profile_read()
     lat.profile(False)
     if args.copy_calibration:
@@ -608,6 +620,10 @@ def main():
             "traffic": traffic,
             "kernel": "k_step2d" if dim == 2 else "k_step1d",
             "avg_launch_us": round(avg_launch_s * 1e6, 3),
+            "launch_timing": ("HIP events around each launch in the timed "
+                              "region" if inline_events else
+                              "HIP events around each launch in a second "
+                              "pass of the K steps after the timed region"),
             "algorithmic_bytes_per_launch": algo_bytes,
         },
     }

@@ -37,6 +37,10 @@ inline bool step2d_offsets_fit(int nv, int64_t nx, int64_t ny, size_t elem) {
 }
 
 hipError_t launch_step1d(const StepArgs& a, hipStream_t s);
+// The split-column 1D pass (P lanes per site) for the velocity lattices it
+// is compiled for; launch_step1d picks it for short lattices.
+bool step1d_parts_supported(int nv, int f64);
+hipError_t launch_step1d_parts(const StepArgs& a, hipStream_t s);
 hipError_t launch_step2d(const StepArgs& a, hipStream_t s);
 
 // Sticky CFL / finiteness check of the u slices: sets flag |= 1 when some

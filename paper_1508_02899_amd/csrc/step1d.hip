@@ -71,8 +71,15 @@ bool step1d_supported(int nv, int f64) {
   return nv >= 3 && (nv & 1) && nv <= (f64 ? 65 : 129);
 }
 
+// Up to this many sites the split-column pass (step1d_parts.hip) runs
+// instead: it keeps P lanes per site busy where one lane per site would
+// leave most of the chip idle.
+constexpr int64_t kPartsMaxSites = 1 << 19;
+
 hipError_t launch_step1d(const StepArgs& a, hipStream_t s) {
   if (!step1d_supported(a.nv, a.f64) || a.nx < 1) return hipErrorInvalidValue;
+  if (a.nx <= kPartsMaxSites && step1d_parts_supported(a.nv, a.f64))
+    return launch_step1d_parts(a, s);
   return a.f64 ? launch_f64(a, s) : launch_f32(a, s);
 }
 

@@ -29,7 +29,36 @@ def test_1d_f32_parity(nv, scheme):
     assert err <= FP32_REL_L2
 
 
-@pytest.mark.parametrize("nv", [3, 9, 33, 65])
+@pytest.mark.parametrize("nx,nv", [(1, 17), (7, 33), (31, 65), (45, 129),
+                                   (64, 33), (65, 17), (1000, 129)])
+def test_1d_split_column_short_and_ragged(nx, nv):
+    """The split-column 1D pass on lattices shorter than one workgroup's
+    sites and with ragged tails; nsub = 3 and stride 4 on the way."""
+    say(f"1d split-column nx={nx} nv={nv}")
+    f0, u, p = make_case(1, nx, nv, seed=300 + nx + nv, slices=2, s=4,
+                         nsub=3)
+    got = run_gpu(f0, u, p, 6, u_hold=3)
+    want = run_oracle(f0, u, p, 6, u_hold=3)
+    err = rel_l2(got, want)
+    say("  rel L2", err)
+    assert err <= FP32_REL_L2
+
+
+@pytest.mark.parametrize("scheme", ["koren", "upwind"])
+def test_1d_long_lattice_one_lane_per_site(scheme):
+    """Past 2^19 sites the 1D pass gives each site one lane (the whole
+    column in registers); nx = 2^19 + 37 with 33 velocities."""
+    nx = (1 << 19) + 37
+    say(f"1d one-lane-per-site nx={nx} nv=33 {scheme}")
+    f0, u, p = make_case(1, nx, 33, seed=401, scheme=scheme)
+    got = run_gpu(f0, u, p, 3)
+    want = run_oracle(f0, u, p, 3)
+    err = rel_l2(got, want)
+    say("  rel L2", err)
+    assert err <= FP32_REL_L2
+
+
+@pytest.mark.parametrize("nv", [3, 9, 17, 33, 65])
 @pytest.mark.parametrize("scheme", ["koren", "upwind"])
 def test_1d_f64_parity(nv, scheme):
     say(f"1d f64 nv={nv} {scheme}")
