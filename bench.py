@@ -52,21 +52,38 @@ WORKLOADS = {
     "coarse-mlp-256x256": dict(dim=2, n=256, nv=65, s=1, dtype="f32", St=2.0,
                                kappa=1e-4, vmax=3.0, coarse=True),
 }
-KERNEL_SOURCES = ["paper_1508_02899_amd/csrc/step2d.h",
-                  "paper_1508_02899_amd/csrc/step1d.hip",
-                  "paper_1508_02899_amd/csrc/device_common.h"]
+# The sources of the step kernel of each dimension: counters recorded in
+# profiles/ count only while these hash to the recorded value.
+KERNEL_SOURCES = {
+    2: ["paper_1508_02899_amd/csrc/step2d.h",
+        "paper_1508_02899_amd/csrc/device_common.h"],
+    1: ["paper_1508_02899_amd/csrc/step1d.hip",
+        "paper_1508_02899_amd/csrc/step1d_parts.hip",
+        "paper_1508_02899_amd/csrc/column1d.h",
+        "paper_1508_02899_amd/csrc/device_common.h"],
+}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_hash() -> str:
+def kernel_hash(dim: int) -> str:
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in KERNEL_SOURCES[dim]:
         with open(os.path.join(ROOT, p), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def step_kernel(dim, n, nv, dtype):
+    """The step kernel the library runs for this lattice (2D: k_step2d; 1D:
+    the split-column pass up to 2^19 sites for the velocity counts it is
+    built for, else one lane per site)."""
+    if dim == 2:
+        return "k_step2d"
+    parts = nv in (17, 33, 65) or (nv == 129 and dtype == "f32")
+    return "k_step1d_parts" if parts and n <= (1 << 19) else "k_step1d"
 
 
 def geometry(w):
@@ -325,7 +342,7 @@ def load_traffic(name):
         return None
     with open(path) as fh:
         t = json.load(fh)
-    if t.get("kernel_hash") != kernel_hash():
+    if t.get("kernel_hash") != kernel_hash(WORKLOADS[name]["dim"]):
         return None  # counters were taken on another version of the kernel
     return t.get("bytes_per_launch")
 
@@ -359,7 +376,7 @@ def summarize(args):
     import statistics
     w = WORKLOADS[args.workload]
     trace, fetch, write = (_rocpd(d) for d in args.summarize)
-    kern = "k_step2d" if w["dim"] == 2 else "k_step1d"
+    kern = step_kernel(w["dim"], w["n"], w["nv"], w["dtype"])
     elem = 8 if w["dtype"] == "f64" else 4
     ny = w["n"] if w["dim"] == 2 else 1
     sites = w["n"] * ny
@@ -395,7 +412,7 @@ def summarize(args):
     fw = state / 1024.0 / w_c
     traffic = (f_k * ff + w_k * fw) * 1024.0
     out = {"workload": args.workload, "kernel": kern,
-           "kernel_hash": kernel_hash(),
+           "kernel_hash": kernel_hash(w["dim"]),
            "bytes_per_launch": round(traffic),
            "read_bytes": round(f_k * ff * 1024.0),
            "write_bytes": round(w_k * fw * 1024.0),
@@ -618,7 +635,7 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": "k_step2d" if dim == 2 else "k_step1d",
+            "kernel": step_kernel(dim, n, nv, w["dtype"]),
             "avg_launch_us": round(avg_launch_s * 1e6, 3),
             "launch_timing": ("HIP events around each launch in the timed "
                               "region" if inline_events else
