@@ -551,10 +551,11 @@ def main():
         run_steps(0, W)
         lat.sync()
     # Launch durations: HIP events around every step launch on the
-    # library's stream.  For the 2D lattices (launches of hundreds of us)
-    # they are taken inside the timed region; a 1D step lasts a few us, and
-    # per-launch events there would add their own latency to the steps, so
-    # they are taken over a second pass of the same K steps right after it.
+    # library's stream, inside the timed region, for the 2D lattices
+    # (launches of hundreds of us).  A 1D step lasts a few us and an event
+    # pair per launch would add its own latency, so there the K launches of
+    # a second pass of the same steps right after the timed region are
+    # timed back to back by one event pair on the same stream.
     inline_events = dim == 2
     torch.cuda.synchronize()
     lat.profile(inline_events)
@@ -568,12 +569,19 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ev_ms = ev0.elapsed_time(ev1)
-    if not inline_events:
-        lat.profile(True)
+    if inline_events:
+        kern_ms, launches = lat.profile_read()
+        lat.profile(False)
+    else:
+        lat.profile(False)
+        ev2 = torch.cuda.Event(enable_timing=True)
+        ev3 = torch.cuda.Event(enable_timing=True)
+        ev2.record()
         run_steps(W, K)
+        ev3.record()
+        torch.cuda.synchronize()
         lat.sync()
-    kern_ms, launches = lat.profile_read()
-    lat.profile(False)
+        kern_ms, launches = ev2.elapsed_time(ev3), K
     if args.copy_calibration:
         g = torch.empty_like(f)
         lat.copy_state(g, f)
@@ -639,8 +647,9 @@ def main():
             "avg_launch_us": round(avg_launch_s * 1e6, 3),
             "launch_timing": ("HIP events around each launch in the timed "
                               "region" if inline_events else
-                              "HIP events around each launch in a second "
-                              "pass of the K steps after the timed region"),
+                              "one HIP event pair around the K back-to-back "
+                              "launches of a second pass of the same steps "
+                              "after the timed region"),
             "algorithmic_bytes_per_launch": algo_bytes,
         },
     }

@@ -313,10 +313,14 @@ int lattice_batch_layout(const lattice_batch_t* B, int64_t* f_off,
                          int64_t* total_u);
 
 /* Work decomposition of one capacity class (cap = 9, 17, 33, 65 or 129):
- * block = lanes (= sites) per tile (64, 128 or 256); grid_per_cu = resident
- * workgroups per compute unit of the persistent launch (1..16, or 0 = one
- * workgroup per tile, not persistent).  Chosen by the autotuner; defaults
- * 256 / 0.  EINVAL. */
+ * block = lanes (= sites) per tile (64, 128 or 256), one lane per site with
+ * its whole velocity column, or 0 = split-column tiles (each column over
+ * several lanes, a tile of consecutive sites staged through LDS; only for
+ * cap 17, 33, 65 or 129 and only when every member of the class has
+ * nv == cap); grid_per_cu = resident workgroups per compute unit of the
+ * persistent launch (1..16, or 0 = one workgroup per tile, not
+ * persistent).  Chosen by the autotuner; defaults 256 / 0.  EINVAL (the
+ * class keeps its previous decomposition). */
 int lattice_batch_tune(lattice_batch_t* B, int32_t cap, int32_t block,
                        int32_t grid_per_cu);
 

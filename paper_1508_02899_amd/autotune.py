@@ -2,10 +2,11 @@
 
 For every velocity-capacity class present in a batch (members with
 nv <= 9, 17, 33, 65, 129), time candidate work decompositions -- lanes per
-tile (64, 128, 256) and resident workgroups per compute unit of the
-persistent launch (0 = one workgroup per tile) -- on the GPU with HIP
-events, on a sub-batch holding only that class's members, and keep the
-fastest.  Results are cached as JSON keyed by GPU architecture, class,
+tile (64, 128, 256: one lane per site), or split-column tiles (block 0:
+each column over several lanes, for classes whose members all have
+nv == cap), and resident workgroups per compute unit of the persistent
+launch (0 = one workgroup per tile) -- on the GPU with HIP events, on a
+sub-batch holding only that class's members, and keep the fastest.  Results are cached as JSON keyed by GPU architecture, class,
 scheme and the class's size (log2 of its cell count), so later batches of
 similar shape reuse them without timing.
 """
@@ -20,7 +21,18 @@ CACHE = os.path.join(HERE, "tuning", "batch1d.json")
 
 CANDIDATES = [(64, 0), (128, 0), (256, 0), (64, 2), (64, 4), (64, 8),
               (128, 1), (128, 2), (128, 4), (256, 1), (256, 2)]
+# split-column tiles (block 0), for the classes that allow them
+SPLIT_CANDIDATES = [(0, 0), (0, 2), (0, 4), (0, 8)]
+SPLIT_CAPS = (17, 33, 65, 129)
 DEFAULT = (256, 0)
+
+
+def candidates(cap: int, nvs) -> list:
+    """Decompositions to time for a class with capacity cap whose members
+    have the velocity counts nvs."""
+    if cap in SPLIT_CAPS and all(nv == cap for nv in nvs):
+        return CANDIDATES + SPLIT_CANDIDATES
+    return list(CANDIDATES)
 
 
 def _arch() -> str:
@@ -95,7 +107,10 @@ def tune_batch(batch, flows, scheme: str = "koren", steps: int = 20,
     dirty = False
     for cap, idx in sorted(classes_of(batch.members).items()):
         cells = sum(batch.members[i].nx * batch.members[i].nv for i in idx)
-        key = _key(arch, cap, scheme, cells)
+        nvs = [batch.members[i].nv for i in idx]
+        # classes that admit split-column tiles have more candidates
+        key = _key(arch, cap, scheme, cells) + (
+            "|split" if len(candidates(cap, nvs)) > len(CANDIDATES) else "")
         if use_cache and key in cache:
             blk, gpc = cache[key]["block"], cache[key]["grid_per_cu"]
             chosen[cap] = (blk, gpc, cache[key].get("ms_per_step"))
@@ -111,7 +126,7 @@ def tune_batch(batch, flows, scheme: str = "koren", steps: int = 20,
                               steps) for m in mems))
         n -= n % 2
         best = None
-        for blk, gpc in CANDIDATES:
+        for blk, gpc in candidates(cap, [m.nv for m in mems]):
             ms = _time_class(sub, f, u, max(n, 2), min(graph_steps, max(n, 2)),
                              blk, gpc)
             if log:

@@ -1,10 +1,13 @@
 // batch1d.hip -- kernels of the batched 1D form: many independent
 // realizations (each its own nx, nv, dt, tau_p, kappa and flow) in one
 // packed state buffer, advanced by persistent kernels that walk a list of
-// (member, tile) work items.  The per-site update is column1d, exactly the
-// single-lattice pass.
+// (member, tile) work items.  The per-site update is column1d (one lane per
+// site) or, for a class whose members all have nv equal to the class
+// capacity, the split-column tile of parts1d.h -- exactly the updates of
+// the single-lattice passes.
 #include "batch_internal.h"
 #include "column1d.h"
+#include "parts1d.h"
 
 namespace lat {
 namespace {
@@ -30,6 +33,87 @@ __global__ __launch_bounds__(256) void k_batch1d(
     column1d<float, CAP, KOREN>(fin + m.f_off, fout + m.f_off, x, m.nx, m.nv,
                                 m.h, m.step_mod, m.init_off, m.nsub,
                                 ux * m.alpha_scale, m.beta, m.D);
+  }
+}
+
+// Parts and wavefronts per workgroup of the batched split-column tiles
+// (timed on configuration 4's classes: nv = 65 prefers longer columns per
+// lane and nv = 129 wider workgroups here than on a single short lattice).
+template <int NV>
+struct BatchShape {
+  static constexpr int P = PartsShape<float, NV>::P;
+  static constexpr int WGW = PartsShape<float, NV>::WGW;
+};
+template <>
+struct BatchShape<65> {
+  static constexpr int P = 4, WGW = 4;
+};
+template <>
+struct BatchShape<129> {
+  static constexpr int P = 8, WGW = 8;
+};
+
+template <int NV>
+constexpr int parts_threads() {
+  return 64 * BatchShape<NV>::WGW;
+}
+
+// Split-column form: work items are tiles of G sites of one member (all
+// members of the class have nv == NV).  Software-pipelined over the work
+// items of a workgroup: the loads of the next tile are issued before the
+// current tile's columns are updated, so that they overlap its collision
+// and its stores.
+template <int NV, bool KOREN>
+__global__ __launch_bounds__(parts_threads<NV>()) void k_batch1d_parts(
+    const float* __restrict__ fin, float* __restrict__ fout,
+    const float* __restrict__ u, const BatchMember* __restrict__ mem,
+    const BatchTile* __restrict__ tiles, int ntiles,
+    const int* __restrict__ mflag, const int* __restrict__ step_base,
+    int local_step) {
+  constexpr int P = BatchShape<NV>::P, WGW = BatchShape<NV>::WGW;
+  using PT = Parts1DTile<float, NV, P, WGW>;
+  __shared__ float tile[NV * PT::STRIDE];
+  const int step = *step_base + local_step;
+  // next work item of this workgroup at or after w, skipping frozen
+  // members (uniform over the workgroup)
+  auto next = [&](int w) {
+    while (w < ntiles && mflag[tiles[w].member] != 0) w += gridDim.x;
+    return w;
+  };
+  auto issue = [&](int w, float (&r)[PT::K], bool idle) {
+    const BatchTile tl = tiles[w];
+    const BatchMember m = mem[tl.member];
+    int jump = 0;  // (P s) mod nx, no division
+    for (int q = 0; q < P; ++q) {
+      jump += m.step_mod;
+      if (jump >= m.nx) jump -= m.nx;
+    }
+    PT::load(fin + m.f_off, m.nx, tl.x0, m.step_mod, m.init_off, jump, r,
+             idle);
+  };
+  float r[PT::K];
+  int w = next((int)blockIdx.x);
+  if (w < ntiles) issue(w, r, false);
+  while (w < ntiles) {
+    const BatchTile tl = tiles[w];
+    const BatchMember m = mem[tl.member];
+    PT::put(tile, r);
+    const int sl = m.u_hold > 0 ? step / m.u_hold : 0;
+    // the flow value first: the memory counter is in order, and the
+    // collision must not wait for the loads of the next tile
+    const float alpha = PT::alpha_at(u + m.u_off + (int64_t)sl * m.nx, m.nx,
+                                     tl.x0, m.alpha_scale);
+    __syncthreads();
+    const int wn = next(w + (int)gridDim.x);
+    // in flight during the update below (unconditional, so that the
+    // counter waits stay exact; past the last item: idle loads of one
+    // element of this member)
+    issue(wn < ntiles ? wn : w, r, wn >= ntiles);
+    PT::template collide<KOREN>(tile, alpha, m.nsub, m.beta, m.D);
+    __syncthreads();
+    PT::store(tile, fout + m.f_off, m.nx, tl.x0);
+    __syncthreads();  // the tile is refilled for the next work item
+    w = wn;
   }
 }
 
@@ -115,9 +199,49 @@ hipError_t launch_cap(const BatchLaunch& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int NV>
+hipError_t launch_parts(const BatchLaunch& a, hipStream_t s) {
+  constexpr int WGW = BatchShape<NV>::WGW;
+  if (a.koren)
+    hipLaunchKernelGGL((k_batch1d_parts<NV, true>), dim3(a.grid),
+                       dim3(64 * WGW), 0, s, a.fin, a.fout, a.u, a.mem,
+                       a.tiles, a.ntiles, a.mflag, a.step_base, a.local_step);
+  else
+    hipLaunchKernelGGL((k_batch1d_parts<NV, false>), dim3(a.grid),
+                       dim3(64 * WGW), 0, s, a.fin, a.fout, a.u, a.mem,
+                       a.tiles, a.ntiles, a.mflag, a.step_base, a.local_step);
+  return hipGetLastError();
+}
+
 }  // namespace
 
+namespace {
+template <int NV>
+constexpr int batch_g() {
+  return Parts1D<float, NV, BatchShape<NV>::P, BatchShape<NV>::WGW>::G;
+}
+}  // namespace
+
+int batch_parts_sites(int cap) {
+  switch (cap) {
+    case 17: return batch_g<17>();
+    case 33: return batch_g<33>();
+    case 65: return batch_g<65>();
+    case 129: return batch_g<129>();
+    default: return 0;
+  }
+}
+
 hipError_t launch_batch1d(const BatchLaunch& a, hipStream_t s) {
+  if (a.block == 0) {  // split-column tiles
+    switch (a.cap) {
+      case 17: return launch_parts<17>(a, s);
+      case 33: return launch_parts<33>(a, s);
+      case 65: return launch_parts<65>(a, s);
+      case 129: return launch_parts<129>(a, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (a.cap) {
     case 9: return launch_cap<9>(a, s);
     case 17: return launch_cap<17>(a, s);

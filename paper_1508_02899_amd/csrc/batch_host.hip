@@ -21,7 +21,7 @@ constexpr int kSide = 3;  // parallel streams for the classes beyond the first
 
 struct Cls {
   int cap = 0;
-  int block = 256;
+  int block = 256;  // sites per tile, one lane each; 0 = split-column tiles
   int gpc = 0;  // resident workgroups per CU (0: one per tile)
   std::vector<int> members;
   lat::BatchTile* d_tiles = nullptr;
@@ -84,8 +84,10 @@ int cap_class(int nv) {
 
 hipError_t build_tiles(lattice_batch_t* B, Cls& c) {
   std::vector<lat::BatchTile> t;
+  const int sites = c.block > 0 ? c.block : lat::batch_parts_sites(c.cap);
+  if (sites <= 0) return hipErrorInvalidValue;
   for (int m : c.members)
-    for (int64_t x0 = 0; x0 < B->desc[m].nx; x0 += c.block)
+    for (int64_t x0 = 0; x0 < B->desc[m].nx; x0 += sites)
       t.push_back({m, (int32_t)x0});
   if (c.d_tiles) (void)hipFree(c.d_tiles);
   c.d_tiles = nullptr;
@@ -324,14 +326,24 @@ int lattice_batch_layout(const lattice_batch_t* B, int64_t* f_off,
 int lattice_batch_tune(lattice_batch_t* B, int32_t cap, int32_t block,
                        int32_t grid_per_cu) {
   if (!B) return LATTICE_EINVAL;
-  if (block != 64 && block != 128 && block != 256)
-    return berr(B, LATTICE_EINVAL, "block must be 64, 128 or 256");
+  if (block != 0 && block != 64 && block != 128 && block != 256)
+    return berr(B, LATTICE_EINVAL, "block must be 0, 64, 128 or 256");
   if (grid_per_cu < 0 || grid_per_cu > 16)
     return berr(B, LATTICE_EINVAL, "grid_per_cu must be 0..16");
   int c = -1;
   for (int i = 0; i < kNumCls; ++i)
     if (kCaps[i] == cap) c = i;
   if (c < 0) return berr(B, LATTICE_EINVAL, "unknown capacity %d", cap);
+  if (block == 0) {
+    if (lat::batch_parts_sites(cap) == 0)
+      return berr(B, LATTICE_EINVAL,
+                  "no split-column kernel for capacity %d", cap);
+    for (int m : B->cls[c].members)
+      if (B->desc[m].nv != cap)
+        return berr(B, LATTICE_EINVAL,
+                    "split-column tiles need nv == %d for every member of "
+                    "the class (member %d has %d)", cap, m, B->desc[m].nv);
+  }
   BCHK(B, hipStreamSynchronize(B->stream));
   B->cls[c].block = block;
   B->cls[c].gpc = grid_per_cu;

@@ -38,7 +38,8 @@ struct BatchPlane {
 struct BatchLaunch {
   int cap;   // velocity capacity class of the kernel (9..129)
   int koren;
-  int block, grid;
+  int block;  // sites per tile, one lane each; 0 = split-column tiles
+  int grid;
   const float* fin;
   float* fout;
   const float* u;
@@ -51,6 +52,9 @@ struct BatchLaunch {
 };
 
 hipError_t launch_batch1d(const BatchLaunch& a, hipStream_t s);
+// Sites per split-column tile of a capacity class (0: no split-column
+// kernel for it).
+int batch_parts_sites(int cap);
 hipError_t launch_batch_cfl(const float* u, const BatchMember* mem, int count,
                             int64_t nsteps, int strict, int* mflag,
                             hipStream_t s);

@@ -102,6 +102,56 @@ def test_batch_graph_replays_and_tuning_are_bit_identical():
     b.close()
 
 
+# members with nv equal to their class capacity (split-column tiles allowed)
+SPLIT_SPECS = [(512, 33, 0.3, 0.2, 2, 0.4), (45, 17, 1.0, 0.3, 0, 0.3),
+               (700, 65, 5.0, 0.05, 1, 0.45), (1000, 129, 10.0, 0.1, 3, 0.4),
+               (31, 129, 2.0, 0.2, 0, 0.35), (8192, 33, 0.1, 0.1, 0, 0.45)]
+
+
+@pytest.mark.parametrize("scheme", ["koren", "upwind"])
+def test_batch_split_column_tiles_match_oracle(scheme):
+    """Split-column tiles (block 0) for every class: members against the
+    oracle, eager and graph replays bit-identical, persistent grids (tiles
+    walked by fewer workgroups) bit-identical to one workgroup per tile."""
+    from paper_1508_02899_amd import Batch
+    nsteps = 8
+    rng = np.random.default_rng(23)
+    mems, states, flows = _members(rng, SPLIT_SPECS, nsteps)
+    b = Batch(mems, scheme=scheme)
+    for cap in (17, 33, 65, 129):
+        b.tune(cap, 0, 0)
+    fp, up = b.pack_state(states), b.pack_flow(flows)
+    ref = _run(b, fp, up, nsteps)
+    for m, f0, u, got in zip(mems, states, flows, b.unpack_state(ref)):
+        want = _oracle_member(m, f0, u, nsteps, scheme)
+        err = rel_l2(got, want)
+        say(f"  member nx={m.nx} nv={m.nv}: rel L2 {err:.2e}")
+        assert err <= FP32_REL_L2
+    for gpc in (1, 4):
+        for cap in (17, 33, 65, 129):
+            b.tune(cap, 0, gpc)
+        assert np.array_equal(_run(b, fp, up, nsteps, graph_steps=4), ref)
+    b.close()
+
+
+def test_batch_split_column_needs_nv_equal_to_capacity():
+    """A class holding a member with nv below its capacity refuses
+    split-column tiles and keeps working with its previous decomposition."""
+    from paper_1508_02899_amd import Batch, LatticeError
+    rng = np.random.default_rng(24)
+    mems, states, flows = _members(rng, [(200, 31, 1.0, 0.2, 0, 0.4),
+                                         (100, 33, 1.0, 0.2, 0, 0.4)], 4)
+    b = Batch(mems)
+    with pytest.raises(LatticeError):
+        b.tune(33, 0, 0)
+    with pytest.raises(LatticeError):
+        b.tune(9, 0, 0)
+    out = b.unpack_state(_run(b, b.pack_state(states), b.pack_flow(flows), 4))
+    for m, f0, u, got in zip(mems, states, flows, out):
+        assert rel_l2(got, _oracle_member(m, f0, u, 4)) <= FP32_REL_L2
+    b.close()
+
+
 def test_batch_moments_match_oracle():
     import torch
     import oracle
