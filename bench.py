@@ -292,7 +292,7 @@ def bench_coarse(args, w):
     ms_fine = timed(fine, ff)
     ms_plain = timed(plain, states["plain"])
     ms_mlp = timed(corr, states["mlp"])
-    # correction kernel on every face (no line skipped): nominal flops
+    # correction kernel on every face (none skipped): nominal flops
     full = Lattice(cs)
     mlp.attach(full, St, 0.0)
     ms_full = timed(full, states["plain"].clone())
@@ -311,8 +311,9 @@ def bench_coarse(args, w):
             "workload": (f"coarse-mlp-256x256: 2D periodic 256^2 sites; fine "
                          f"{nvf}^2 velocities (nsub {nsf}) vs stride-4 coarse "
                          f"17^2 (nsub {nsc}) + learned face-flux correction "
-                         "(8-64-64-1 GELU, bf16 matrix cores, lines below "
-                         f"1e-3 of the site mass skipped), St={St}, "
+                         "(8-64-64-1 GELU, bf16 matrix cores, faces whose "
+                         "stencil holds below 1e-3 of the site mass "
+                         f"skipped), St={St}, "
                          f"kappa={kappa}, Vmax={w['vmax']} u_rms, koren; value"
                          " = fine-lattice cell updates per second delivered "
                          "by the coarse model"),

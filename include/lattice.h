@@ -356,8 +356,9 @@ int lattice_batch_destroy(lattice_batch_t* B);
  * one (vstride 4, nv_c = (nv_f - 1)/4 + 1, dv_c = 4 dv_f), so its streaming
  * stays exact (Sec. 2).  With a network attached (lattice_mlp_attach), every
  * lattice_step time step of a 2D nv = 17 FP32 lattice is followed by a
- * correction: for each site and each interior velocity face of every line
- * carrying at least line_eps of the site's mass, the network maps the
+ * correction: for each site and each interior velocity face whose 5-cell
+ * stencil holds at least line_eps of the site's mass (the faces the
+ * training samples of lattice_mlp_samples keep), the network maps the
  * face's 8 features [5-cell stencil from the upwind side / its mass m_s,
  * |face drift| in cells per step, ln St, 0] to y; the face flux
  * sign * m_s * y, limited to a quarter of the donor cell's mass, updates the

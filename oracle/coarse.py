@@ -222,21 +222,18 @@ def face_features(fc, nv, ux, uy, dv, dt, tau_p, St):
 
 def corrected_site(fc, nv, y, ms, sg, line_eps=0.0):
     """Apply the face fluxes G = sg * ms * y, each limited to a quarter of
-    its donor cell's mass, as the conservative update f -= div G.  Velocity
-    lines (rows for x-faces, columns for y-faces) holding less than
-    line_eps of the site's mass (or none) get no correction."""
+    its donor cell's mass, as the conservative update f -= div G.  Faces
+    whose stencil holds less than line_eps of the site's mass (or none) get
+    no correction: the faces the network is trained on are exactly the
+    others (the training samples use the same rule)."""
     c = np.asarray(fc, dtype=np.float64).reshape(nv, nv).copy()
-    G = sg * ms * np.asarray(y, dtype=np.float64)
+    M = c.sum()
+    ms = np.asarray(ms, dtype=np.float64)
+    use = (ms > 0) & (ms >= line_eps * M)
+    G = np.where(use, sg * ms * np.asarray(y, dtype=np.float64), 0.0)
     nfx = nv * (nv - 1)
     Gx = G[:nfx].reshape(nv, nv - 1).copy()   # [jy, k-1]
     Gy = G[nfx:].reshape(nv - 1, nv).T.copy()  # -> [jx, k-1]
-    M = c.sum()
-    for a in range(nv):
-        row, colm = c[a, :].sum(), c[:, a].sum()
-        if not (row >= line_eps * M and row > 0):
-            Gx[a, :] = 0.0
-        if not (colm >= line_eps * M and colm > 0):
-            Gy[a, :] = 0.0
     Gx2 = np.zeros((nv, nv + 1))
     Gy2 = np.zeros((nv + 1, nv))
     for a in range(nv):

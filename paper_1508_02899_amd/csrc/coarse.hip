@@ -37,11 +37,14 @@ __device__ __forceinline__ float qbf(float f) { return bf2f(f2bf(f)); }
 // with the identity 0.5 (1 + tanh(y)) = 1 / (1 + exp(-2y)): one exponential
 // and one approximate reciprocal (1 ulp) per value, no division.  For very
 // negative z, exp overflows to +inf and the reciprocal gives 0 (gelu -> -0).
+// The argument -2 log2(e) y with y = a z (1 + c z^2) is formed as
+// z (K1 + K2 z^2): one multiply-add and one multiply.
 __device__ __forceinline__ float gelu_sig(float z, float z2) {
-  const float a = 0.7978845608028654f, c = 0.044715f;
-  const float k = -2.0f * 1.4426950408889634f;  // -2 log2(e)
-  const float y = a * z * __builtin_fmaf(c, z2, 1.0f);
-  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(k * y));
+  constexpr float a = 0.7978845608028654f, c = 0.044715f;
+  constexpr float K1 = -2.0f * 1.4426950408889634f * a;  // -2 log2(e) a
+  constexpr float K2 = K1 * c;
+  return __builtin_amdgcn_rcpf(
+      1.0f + __builtin_amdgcn_exp2f(z * __builtin_fmaf(K2, z2, K1)));
 }
 __device__ __forceinline__ float gelu(float z) {
   return z * gelu_sig(z, z * z);
@@ -60,13 +63,17 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
+// Four floats to bf16, round to nearest even: two packed hardware
+// conversions (v_cvt_pk_bf16_f32), the same rounding as f2bf.
+typedef __bf16 bf16x2h __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ bf16x4 pack4(float a, float b, float c, float d) {
-  bf16x4 r;
-  r[0] = (short)f2bf(a);
-  r[1] = (short)f2bf(b);
-  r[2] = (short)f2bf(c);
-  r[3] = (short)f2bf(d);
-  return r;
+  const f32x2 lo = {a, b}, hi = {c, d};
+  const u32x2 w = {
+      __builtin_bit_cast(unsigned, __builtin_convertvector(lo, bf16x2h)),
+      __builtin_bit_cast(unsigned, __builtin_convertvector(hi, bf16x2h))};
+  return __builtin_bit_cast(bf16x4, w);
 }
 
 // The network in matrix-core form.  16 inputs (faces) per wavefront pass;
@@ -116,27 +123,27 @@ __device__ void load_mlp(MlpRegs& R, const float* __restrict__ P,
 
 // x = this lane's 4 features (k = 4(l/16)+i of input column l%16; zero for
 // l >= 32).  Returns the output of column l%16 in lanes 0..15.
+// The biases enter as the accumulator inputs of the first matrix-core
+// step of each layer.
 __device__ __forceinline__ float mlp_forward(const MlpRegs& R, bf16x4 x) {
-  const f32x4 z = {0.f, 0.f, 0.f, 0.f};
   bf16x4 h1[4], h2[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    const f32x4 d = mfma16(R.a1[u], x, z);
-    h1[u] = pack4(gelu(d[0] + R.b1[u][0]), gelu(d[1] + R.b1[u][1]),
-                  gelu(d[2] + R.b1[u][2]), gelu(d[3] + R.b1[u][3]));
+    const f32x4 b = {R.b1[u][0], R.b1[u][1], R.b1[u][2], R.b1[u][3]};
+    const f32x4 d = mfma16(R.a1[u], x, b);
+    h1[u] = pack4(gelu(d[0]), gelu(d[1]), gelu(d[2]), gelu(d[3]));
   }
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    f32x4 d = z;
+    f32x4 d = {R.b2[u][0], R.b2[u][1], R.b2[u][2], R.b2[u][3]};
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) d = mfma16(R.a2[u][kk], h1[kk], d);
-    h2[u] = pack4(gelu(d[0] + R.b2[u][0]), gelu(d[1] + R.b2[u][1]),
-                  gelu(d[2] + R.b2[u][2]), gelu(d[3] + R.b2[u][3]));
+    h2[u] = pack4(gelu(d[0]), gelu(d[1]), gelu(d[2]), gelu(d[3]));
   }
-  f32x4 y = z;
+  f32x4 y = {R.b3, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) y = mfma16(R.a3[kk], h2[kk], y);
-  return y[0] + R.b3;
+  return y[0];
 }
 
 // -------------------------------------------------------------- restriction
@@ -488,21 +495,36 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ P
 // ---------------------------------------------------- fused correction
 // 17^2 coarse velocities.  A workgroup loads a tile of TS sites (coalesced,
 // all 289 planes) into LDS; each wavefront corrects its sites one at a
-// time: every velocity line with at least line_eps of the site's mass gets
-// its 16 interior face fluxes from one matrix-core pass; the limited fluxes
-// update the site's cells; the tile is stored back.
+// time: the interior faces whose 5-cell stencil holds at least line_eps of
+// the site's mass (the faces the network is trained on) are gathered into
+// a queue (ballot + prefix count), the queue goes through the matrix cores
+// 16 faces per pass, the limited fluxes update the site's cells; the tile
+// is stored back.
 constexpr int kNVC = 17;
 constexpr int kTS = 32;
+
+// interior face id -> (axis, line, face): x-faces (line = row Jy, face k
+// between columns k-1 | k) first, then y-faces (line = column Jx)
+__device__ __forceinline__ void face_of(int fid, int* axis, int* a, int* k) {
+  constexpr int NFX = kNVC * (kNVC - 1);
+  const int ax = fid >= NFX;
+  const int r = fid - ax * NFX;
+  *axis = ax;
+  *a = r / (kNVC - 1);
+  *k = r - *a * (kNVC - 1) + 1;
+}
 
 __global__ __launch_bounds__(256) void k_mlp_correct17(
     CoarseGeom g, const float* __restrict__ P, const uint16_t* __restrict__ wq,
     float* __restrict__ f, const float* __restrict__ u,
     const int* __restrict__ flag) {
   constexpr int NV = kNVC, N2 = NV * NV;
+  constexpr int NFACE = 2 * NV * (NV - 1);
   __shared__ float tile[N2][kTS + 1];
   __shared__ float gx[4][NV][NV + 1];  // x-face fluxes [row][face 0..NV]
   __shared__ float gy[4][NV + 1][NV];  // y-face fluxes [face 0..NV][col]
-  __shared__ float lm[4][2 * NV];      // line masses
+  __shared__ float lm[4][NV];          // row masses
+  __shared__ uint16_t queue[4][NFACE];
   if (*flag != 0) return;
   MlpRegs R;
   load_mlp(R, P, wq);
@@ -516,18 +538,25 @@ __global__ __launch_bounds__(256) void k_mlp_correct17(
   }
   __syncthreads();
   const int col = l & 15, ks = l >> 4;
+  const uint64_t below = (l == 0) ? 0ull : (~0ull >> (64 - l));
   for (int s = w; s < nts; s += 4) {
     const int64_t site = s0 + s;
     const float ux = u[site], uy = u[S + site];
-    // line masses: rows (lanes 0..16), columns (lanes 32..48)
-    if (l < NV) {
+    auto feat = [&](int fid, float* st, float* ms, float* sg, float* anu) {
+      int axis, a, k;
+      face_of(fid, &axis, &a, &k);
+      if (axis == 0) {
+        auto ln = [&](int c) { return tile[a * NV + c][s]; };
+        face_feat(ln, NV, k, ux, g, st, ms, sg, anu);
+      } else {
+        auto ln = [&](int c) { return tile[c * NV + a][s]; };
+        face_feat(ln, NV, k, uy, g, st, ms, sg, anu);
+      }
+    };
+    if (l < NV) {  // row masses, then the site mass in a fixed order
       float m = 0.f;
       for (int j = 0; j < NV; ++j) m += tile[l * NV + j][s];
       lm[w][l] = m;
-    } else if (l >= 32 && l < 32 + NV) {
-      float m = 0.f;
-      for (int j = 0; j < NV; ++j) m += tile[j * NV + (l - 32)][s];
-      lm[w][NV + l - 32] = m;
     }
     for (int i = l; i < NV * (NV + 1); i += 64) {
       (&gx[w][0][0])[i] = 0.f;
@@ -538,28 +567,40 @@ __global__ __launch_bounds__(256) void k_mlp_correct17(
     float M = 0.f;
     for (int j = 0; j < NV; ++j) M += lm[w][j];
     const float thr = g.line_eps * M;
-    for (int line = 0; line < 2 * NV; ++line) {
-      if (!(lm[w][line] >= thr) || !(lm[w][line] > 0.f)) continue;  // uniform
-      const int axis = line >= NV, a = line - axis * NV;
-      const int k = col + 1;  // face of this lane's column
-      float st[5], ms, sg, anu;
-      if (axis == 0) {
-        auto ln = [&](int c) { return tile[a * NV + c][s]; };
-        face_feat(ln, NV, k, ux, g, st, &ms, &sg, &anu);
-      } else {
-        auto ln = [&](int c) { return tile[c * NV + a][s]; };
-        face_feat(ln, NV, k, uy, g, st, &ms, &sg, &anu);
+    // queue of the faces that get a correction
+    int nq = 0;
+    for (int f0 = 0; f0 < NFACE; f0 += 64) {
+      const int fid = f0 + l;
+      bool use = false;
+      if (fid < NFACE) {
+        float st[5], ms, sg, anu;
+        feat(fid, st, &ms, &sg, &anu);
+        use = ms > kMinStencilMass && ms >= thr;
       }
+      const uint64_t b = __ballot(use);
+      if (use) queue[w][nq + __popcll(b & below)] = (uint16_t)fid;
+      nq += __popcll(b);
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    for (int c0 = 0; c0 < nq; c0 += 16) {
+      const int e = c0 + col;
+      const bool live = e < nq;
+      const int fid = live ? (int)queue[w][e] : 0;
+      float st[5], ms, sg, anu;
+      feat(fid, st, &ms, &sg, &anu);
       const float inv = ms > 0.f ? 1.0f / ms : 0.f;
       bf16x4 x;
-      if (ks == 0)
+      if (ks == 0 && live)
         x = pack4(st[0] * inv, st[1] * inv, st[2] * inv, st[3] * inv);
-      else if (ks == 1)
+      else if (ks == 1 && live)
         x = pack4(st[4] * inv, anu, g.log_st, 0.f);
       else
         x = pack4(0.f, 0.f, 0.f, 0.f);
       const float y = mlp_forward(R, x);
-      if (l < 16) {
+      if (l < 16 && live) {
+        int axis, a, k;
+        face_of(fid, &axis, &a, &k);
         float G = sg * ms * y;
         const float donor = axis == 0 ? tile[a * NV + (G > 0.f ? k - 1 : k)][s]
                                       : tile[(G > 0.f ? k - 1 : k) * NV + a][s];
