@@ -59,6 +59,7 @@ KERNEL_SOURCES = {
         "paper_1508_02899_amd/csrc/device_common.h"],
     1: ["paper_1508_02899_amd/csrc/step1d.hip",
         "paper_1508_02899_amd/csrc/step1d_parts.hip",
+        "paper_1508_02899_amd/csrc/parts1d.h",
         "paper_1508_02899_amd/csrc/column1d.h",
         "paper_1508_02899_amd/csrc/device_common.h"],
 }
@@ -368,6 +369,42 @@ def _counter(db, counter, pattern):
     return [r[0] for r in rows]
 
 
+def _trace_table(trace, workload, cmd):
+    """Kernel-time table of a rocprofv3 --kernel-trace --stats run."""
+    top = trace.execute("select name, total_calls, total_duration, average, "
+                        "percentage from top_kernels order by total_duration "
+                        "desc").fetchall()
+    lines = [f"# rocprofv3 --kernel-trace --stats: {workload}", "",
+             "command (from the repository root):", "", "    " + cmd, "",
+             "| kernel | calls | total us | average us | % |",
+             "|---|---|---|---|---|"]
+    for nm, calls, tot, avg, pct in top:
+        short = nm.replace("(anonymous namespace)::", "").split("(")[0]
+        lines.append(f"| `{short}` | {calls} | {tot:.1f} | {avg:.1f} | "
+                     f"{pct:.1f} |")
+    return top, lines
+
+
+# dominant kernel family of the workloads whose summaries hold only the
+# kernel-time table
+TRACE_ONLY_KERNELS = {"batch-256x1d": "k_batch1d",
+                      "coarse-mlp-256x256": "k_mlp_correct17"}
+
+
+def summarize_trace(args):
+    """Write the kernel-time summary of one workload under profiles/ from a
+    rocprofv3 --kernel-trace --stats output folder."""
+    kern = TRACE_ONLY_KERNELS[args.workload]
+    cmd = args.command or "(command not recorded)"
+    _, lines = _trace_table(_rocpd(args.summarize_trace), args.workload, cmd)
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    path = os.path.join(ROOT, "profiles",
+                        f"{kern}_{args.workload}_kernel_stats.md")
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(path)
+
+
 def summarize(args):
     """Write the kernel-time and HBM-byte summaries of one workload under
     profiles/ from rocprofv3 output folders.  HBM bytes: the FETCH_SIZE and
@@ -387,18 +424,9 @@ def summarize(args):
     name = f"{kern}_{args.workload}"
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     cmd = args.command or "(command not recorded)"
-    top = trace.execute("select name, total_calls, total_duration, average, "
-                        "percentage from top_kernels order by total_duration "
-                        "desc").fetchall()
-    lines = [f"# rocprofv3 --kernel-trace --stats: {args.workload}", "",
-             "command (from the repository root):", "", "    " + cmd, "",
-             "| kernel | calls | total us | average us | % |",
-             "|---|---|---|---|---|"]
+    top, lines = _trace_table(trace, args.workload, cmd)
     avg_us = None
     for nm, calls, tot, avg, pct in top:
-        short = nm.replace("(anonymous namespace)::", "").split("(")[0]
-        lines.append(f"| `{short}` | {calls} | {tot:.1f} | {avg:.1f} | "
-                     f"{pct:.1f} |")
         if avg_us is None and kern in nm:
             avg_us = avg
     with open(os.path.join(ROOT, "profiles", f"{name}_kernel_stats.md"),
@@ -470,11 +498,17 @@ def main():
                          "(--kernel-trace --stats, --pmc FETCH_SIZE, --pmc "
                          "WRITE_SIZE, each run with --copy-calibration) and "
                          "write the summaries under profiles/")
+    ap.add_argument("--summarize-trace", metavar="TRACE",
+                    help="no GPU run: kernel-time summary only, from one "
+                         "rocprofv3 --kernel-trace --stats folder (batched "
+                         "and coarse workloads)")
     ap.add_argument("--command", default="",
                     help="with --summarize: the command line that made them")
     args = ap.parse_args()
     if args.summarize:
         return summarize(args)
+    if args.summarize_trace:
+        return summarize_trace(args)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the lattice update runs on a single "
