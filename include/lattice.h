@@ -399,6 +399,28 @@ int lattice_mlp_samples(lattice_t* L, double dt, double tau_p, double St,
                         const float* u, const int32_t* sites, int64_t nsites,
                         float* X, float* t, float* w);
 
+/* Training samples with natural flux targets at nsites listed sites of the
+ * coarse lattice L (2D, nv 17, FP32) of the fine lattice `fine` (2D, nv 65,
+ * FP32, same sites and dx, vstride 4x smaller).  f_fine = the fine state
+ * after streaming, before its collision ([65^2][ny][nx]); f_pred = the
+ * coarse collision (lattice_collide of L) of its restriction
+ * ([17^2][ny][nx]); u the flow slice [2][ny][nx]; all device.  Per site the
+ * fine collision (fine's nsub and scheme, coefficients of Eqs. 4, 5 with
+ * tau_p, kappa, dt) is repeated with its face fluxes F recorded; the
+ * target fluxes are the coarse fluxes implied by F under the restriction
+ * R (div_c G = R div F) minus the face fluxes of the coarse collision of
+ * R f_fine (L's nsub and scheme), so that f_pred - div T = R (fine
+ * collision of f_fine).  X, t, w as in lattice_mlp_samples (features and
+ * weights from f_pred; the same face rule with rel_eps).  These targets
+ * are face-local (the fine fluxes near the face), unlike the least-norm
+ * ones.  Asynchronous on L's stream.  EINVAL, ENOTSUP, EHIP. */
+int lattice_mlp_samples_natural(const lattice_t* fine, lattice_t* L,
+                                double dt, double tau_p, double kappa,
+                                double St, double rel_eps,
+                                const float* f_fine, const float* f_pred,
+                                const float* u, const int32_t* sites,
+                                int64_t nsites, float* X, float* t, float* w);
+
 /* Gradient of L = sum w (y - t)^2 / sum w over n samples (device X[n][8],
  * t, w) into grad (device, 4801 floats, may be NULL) and *loss (host);
  * weights and layer inputs rounded to bf16 as in the forward pass.

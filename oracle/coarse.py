@@ -19,6 +19,9 @@ streaming is still an exact integer shift.  Fine nv_f = 4 (nv_c - 1) + 1.
 * the flux-correction MLP: x (8) -> 64 -> 64 -> 1, GELU (tanh form,
   Hendrycks & Gimpel 2016: 0.5 z (1 + tanh(sqrt(2/pi)(z + 0.044715 z^3)))),
   forward and hand-derived backward, weighted squared loss, Adam.
+* natural flux targets: the collision of a site with its face fluxes
+  recorded, and the coarse fluxes those imply under the restriction
+  (div_c G = R div F), minus the coarse collision's own fluxes.
 * face features and the corrected coarse update.
 """
 from __future__ import annotations
@@ -99,6 +102,120 @@ def minnorm_fluxes(r: np.ndarray, n: int) -> tuple[np.ndarray, np.ndarray]:
     G, *_ = np.linalg.lstsq(D, -r, rcond=None)
     nfx = n * (n - 1)
     return G[:nfx].reshape(n, n - 1, -1), G[nfx:].reshape(n - 1, n, -1)
+
+
+# ---------------------------------------------------------------------------
+# collision of one site with its face fluxes, and the natural coarse fluxes
+def _limiter(dp, dm):
+    """Koren limiter in the division-free form: dp > 0: max(0, min(dp,
+    dp/3 + dm/6, dm)); dp < 0: min(0, max(...)); dp = 0: 0."""
+    t = dp / 3.0 + dm / 6.0
+    up = np.maximum(0.0, np.minimum(np.minimum(dp, t), dm))
+    dn = np.minimum(0.0, np.maximum(np.maximum(dp, t), dm))
+    return np.where(dp > 0, up, np.where(dp < 0, dn, 0.0))
+
+
+def _drift_faces(c, nu, koren):
+    """Split drift fluxes of lines c[..., n] with cell-centred nu[n] (Eq. 5
+    force in cells per sub-step): F[..., k] through face k (cells k-1 | k),
+    k = 0..n, the outer faces closed, cells outside the line empty."""
+    n = c.shape[-1]
+    pad = [(0, 0)] * (c.ndim - 1) + [(2, 2)]
+    gp = np.pad(np.maximum(nu, 0.0) * c, pad)   # gp[i + 2] = g+ of cell i
+    gm = np.pad(np.minimum(nu, 0.0) * c, pad)
+    F = np.zeros(c.shape[:-1] + (n + 1,))
+    for k in range(1, n):
+        fp = gp[..., k + 1]                     # g+ of cell k-1
+        fm = gm[..., k + 2]                     # g- of cell k
+        if koren:
+            fp = fp + _limiter(gp[..., k + 2] - gp[..., k + 1],
+                               gp[..., k + 1] - gp[..., k])
+            fm = fm + _limiter(gm[..., k + 1] - gm[..., k + 2],
+                               gm[..., k + 2] - gm[..., k + 3])
+        F[..., k] = fp + fm
+    return F
+
+
+def _diffusion_faces(c, D):
+    """Diffusion fluxes D (c_{k-1} - c_k) through faces k = 1..n-1."""
+    n = c.shape[-1]
+    F = np.zeros(c.shape[:-1] + (n + 1,))
+    F[..., 1:n] = D * (c[..., :-1] - c[..., 1:])
+    return F
+
+
+def collide_site(c, ux, uy, alpha_scale, beta, D, nsub, koren=True):
+    """The collision part of one 2D time step at one site (Sec. 2: nsub x
+    [drift along vx, drift along vy, diffusion along vx, along vy], the
+    force at cell centres, nu_j = alpha_scale u - beta (j - h)), on its
+    velocity square c[jy, jx].  Returns (c after, Fx[jy, 0..nv] summed over
+    the sub-steps, Fy[0..nv, jx] summed): c_after = c - div F exactly."""
+    c = np.asarray(c, dtype=np.float64).copy()
+    nv = c.shape[0]
+    h = (nv - 1) // 2
+    j = np.arange(nv) - h
+    nux = alpha_scale * ux - beta * j
+    nuy = alpha_scale * uy - beta * j
+    Fx = np.zeros((nv, nv + 1))
+    Fy = np.zeros((nv + 1, nv))
+    for _ in range(nsub):
+        F = _drift_faces(c, nux, koren)                 # rows: along vx
+        c -= F[:, 1:] - F[:, :-1]
+        Fx += F
+        F = _drift_faces(c.T, nuy, koren).T             # columns: along vy
+        c -= F[1:, :] - F[:-1, :]
+        Fy += F
+        F = _diffusion_faces(c, D)
+        c -= F[:, 1:] - F[:, :-1]
+        Fx += F
+        F = _diffusion_faces(c.T, D).T
+        c -= F[1:, :] - F[:-1, :]
+        Fy += F
+    return c, Fx, Fy
+
+
+def natural_coarse_fluxes(Fx, Fy):
+    """Coarse face fluxes G with div_c G = R (div F) for the stride-4
+    restriction R (restrict_weights, densities / 4 per axis): coarse face k
+    (coarse cells k-1 | k) collects the fine faces 4k-2 and 4k-1 on either
+    side of the shared fine cell 4k-2, G_k = (F_{4k-2} + F_{4k-1}) / 8 per
+    fine line, and the lines are combined with the restriction weights
+    across the other axis.  Fx[jy, 0..nv_f], Fy[0..nv_f, jx] ->
+    (Gx[Jy, 0..nv_c], Gy[0..nv_c, Jx])."""
+    nv_f = Fx.shape[0]
+    R = restrict_weights(nv_f) / 4.0
+    nv_c = R.shape[0]
+    k = np.arange(1, nv_c)
+    ax = np.zeros((nv_f, nv_c + 1))
+    ax[:, 1:nv_c] = (Fx[:, 4 * k - 2] + Fx[:, 4 * k - 1]) / 8.0
+    Gx = R @ ax                                      # [Jy, faces]
+    ay = np.zeros((nv_c + 1, nv_f))
+    ay[1:nv_c, :] = (Fy[4 * k - 2, :] + Fy[4 * k - 1, :]) / 8.0
+    Gy = ay @ R.T                                    # [faces, Jx]
+    return Gx, Gy
+
+
+def natural_targets(g_fine, ux, uy, fine, coarse):
+    """Target face fluxes of one site from its streamed fine velocity square
+    g_fine[nv_f*nv_f]: the natural coarse fluxes of the fine collision minus
+    the coarse collision's own fluxes on R g.  fine / coarse: dicts with
+    alpha_scale, beta, D, nsub, koren.  Returns (T in the face order of
+    face_features / divergence_matrix, pred = coarse collision of R g,
+    true = R (fine collision of g)); pred - div T = true."""
+    nv_f = int(round(len(g_fine) ** 0.5))
+    c = np.asarray(g_fine, dtype=np.float64).reshape(nv_f, nv_f)
+    cf, Fx, Fy = collide_site(c, ux, uy, fine["alpha_scale"], fine["beta"],
+                              fine["D"], fine["nsub"], fine["koren"])
+    Gx, Gy = natural_coarse_fluxes(Fx, Fy)
+    rg = restrict(c.reshape(-1, 1), 2).reshape(Gx.shape[0], -1)
+    pred, Cx, Cy = collide_site(rg, ux, uy, coarse["alpha_scale"],
+                                coarse["beta"], coarse["D"], coarse["nsub"],
+                                coarse["koren"])
+    nv = rg.shape[0]
+    Tx, Ty = Gx - Cx, Gy - Cy
+    T = np.concatenate([Tx[:, 1:nv].reshape(-1), Ty[1:nv, :].reshape(-1)])
+    true = restrict(cf.reshape(-1, 1), 2).reshape(nv, nv)
+    return T, pred, true
 
 
 # ---------------------------------------------------------------------------

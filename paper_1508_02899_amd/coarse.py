@@ -45,7 +45,7 @@ def collect_samples(fine: Lattice, coarse: Lattice, mlp: Mlp, f_fine, flow,
                     *, steps: int, dt: float, tau_p: float, kappa: float,
                     St: float, sites_per_step: int, seed: int = 0,
                     first_step: int = 0, rel_eps: float = 1e-3,
-                    collision_only: bool = True):
+                    collision_only: bool = True, targets: str = "minnorm"):
     """Advance the fine state ``steps`` steps (in place) and return the
     training samples (X, t, w) of ``sites_per_step`` random sites per step.
     ``flow(n)`` gives the flow slice [1, dim, ny, nx] of step n; the coarse
@@ -56,7 +56,20 @@ def collect_samples(fine: Lattice, coarse: Lattice, mlp: Mlp, f_fine, flow,
     streamed state, R C_f (S_f f_n) against C_c (R S_f f_n), which leaves
     out the (velocity-space unrepresentable) difference between fine and
     coarse streaming; otherwise the whole steps, R f_{n+1} against
-    C(R f_n)."""
+    C(R f_n).
+
+    targets: "minnorm" (default): the least-norm face fluxes of the
+    residual; "natural" (collision_only only): the coarse face fluxes
+    implied by the fine collision's own face fluxes under the restriction,
+    minus the coarse collision's fluxes.  Both have the same divergence;
+    the natural ones are face-local and fit far better (about 70 % of
+    their weighted variance explained against 31 %), but the coarse runs
+    corrected by a network trained on them drift further from the fine
+    state (128^2, St = 2: variance error 25 % against 19 %)."""
+    if targets not in ("natural", "minnorm"):
+        raise ValueError("targets: 'natural' or 'minnorm'")
+    if targets == "natural" and not collision_only:
+        raise ValueError("natural targets compare the collision parts")
     torch = _torch()
     dim = fine.spec.dim
     nsites = fine.spec.nx * (fine.spec.ny if dim == 2 else 1)
@@ -66,6 +79,19 @@ def collect_samples(fine: Lattice, coarse: Lattice, mlp: Mlp, f_fine, flow,
     Xs, ts, ws = [], [], []
     for n in range(first_step, first_step + steps):
         u = flow(n)
+        if collision_only and targets == "natural":
+            streamer.step(f_fine, u, math.inf, 0.0, dt, 1)  # S_f f_n
+            fc = restrict(f_fine, dim)                      # R S_f f_n
+            coarse.collide(fc, u, tau_p, kappa, dt, 1)      # C_c(R S_f f_n)
+            sites = torch.randint(0, nsites, (sites_per_step,), generator=gen,
+                                  device=f_fine.device, dtype=torch.int32)
+            X, t, w = mlp.samples_natural(fine, coarse, dt, tau_p, kappa, St,
+                                          f_fine, fc, u, sites, rel_eps)
+            fine.collide(f_fine, u, tau_p, kappa, dt, 1)    # f_{n+1}
+            Xs.append(X)
+            ts.append(t)
+            ws.append(w)
+            continue
         if collision_only:
             streamer.step(f_fine, u, math.inf, 0.0, dt, 1)  # S_f f_n
             fc = restrict(f_fine, dim)                      # R S_f f_n

@@ -17,6 +17,7 @@
 #include <math.h>
 
 #include "coarse_internal.h"
+#include "device_common.h"
 #include "lattice_internal.h"
 
 namespace lat {
@@ -298,6 +299,183 @@ __global__ __launch_bounds__(320) void k_flux_samples(
       G = r[(k - 1) * NV + jx] - r[k * NV + jx];
     }
     // faces with (next to) no mass in the stencil carry no sample weight
+    const bool use = ms > kMinStencilMass && ms >= g.line_eps * msite;
+    const float inv = use ? 1.0f / ms : 0.f;
+    float* x = X + (base + f) * kNF;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) x[i] = st[i] * inv;
+    x[5] = anu;
+    x[6] = g.log_st;
+    x[7] = 0.f;
+    T[base + f] = use ? sg * G * inv : 0.f;
+    Wt[base + f] = use ? ms : 0.f;
+  }
+}
+
+// ------------------------------------------------- natural flux targets
+// The collision of one site's velocity square c[NV][NV] (row jy, column jx)
+// held in LDS, with the face fluxes of every sub-operation summed into
+// Fx[jy][face 0..NV] and Fy[face 0..NV][jx]: the sub-steps of the lattice
+// pass (drift along vx, along vy, diffusion along vx, along vy; force at
+// cell centres, split fluxes with the Koren correction, outer faces
+// closed), so that c_after = c_before - div F.  tmp: NV (NV+1) floats.
+struct CollideCoef {
+  float ax, ay;  // drift of the zero-velocity cell, per axis (cells)
+  float beta, D;
+  int nsub, koren;
+};
+
+template <int NV>
+__device__ void collide_record(float* __restrict__ c, float* __restrict__ tmp,
+                               float* __restrict__ Fx, float* __restrict__ Fy,
+                               const CollideCoef& p) {
+  constexpr int H = (NV - 1) / 2, NF = NV * (NV + 1);
+  const int tid = (int)threadIdx.x, bd = (int)blockDim.x;
+  for (int i = tid; i < NF; i += bd) Fx[i] = Fy[i] = 0.f;
+  __syncthreads();
+  for (int sub = 0; sub < p.nsub; ++sub) {
+    for (int pass = 0; pass < 4; ++pass) {
+      const bool xa = (pass & 1) == 0, drift = pass < 2;
+      const float al = xa ? p.ax : p.ay;
+      for (int q = tid; q < NF; q += bd) {  // face k of line a
+        const int a = q / (NV + 1), k = q - a * (NV + 1);
+        auto cell = [&](int i) {
+          return (i < 0 || i >= NV) ? 0.f : c[xa ? a * NV + i : i * NV + a];
+        };
+        auto nu = [&](int i) {
+          return __builtin_fmaf(-p.beta, (float)(i - H), al);
+        };
+        auto gp = [&](int i) { return pos(nu(i)) * cell(i); };
+        auto gm = [&](int i) { return neg(nu(i)) * cell(i); };
+        float fl = 0.f;
+        if (k >= 1 && k <= NV - 1) {
+          if (drift) {
+            float fp = gp(k - 1), fm = gm(k);
+            if (p.koren) {
+              fp += koren(gp(k) - gp(k - 1), gp(k - 1) - gp(k - 2));
+              fm += koren(gm(k - 1) - gm(k), gm(k) - gm(k + 1));
+            }
+            fl = fp + fm;
+          } else {
+            fl = p.D * (cell(k - 1) - cell(k));
+          }
+        }
+        tmp[q] = fl;
+      }
+      __syncthreads();
+      for (int q = tid; q < NV * NV; q += bd) {
+        const int a = q / NV, i = q - a * NV;
+        c[xa ? a * NV + i : i * NV + a] -=
+            tmp[a * (NV + 1) + i + 1] - tmp[a * (NV + 1) + i];
+      }
+      for (int q = tid; q < NF; q += bd) {
+        const int a = q / (NV + 1), k = q - a * (NV + 1);
+        if (xa)
+          Fx[a * (NV + 1) + k] += tmp[q];
+        else
+          Fy[k * NV + a] += tmp[q];
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Stride-4 restriction weight of fine offset o = j - 4J (|o| <= 2), with the
+// density factor 1/4 of the 4x wider coarse cell.
+__device__ __forceinline__ float rweight(int o) {
+  return (o == -2 || o == 2) ? 0.125f : 0.25f;
+}
+
+// One workgroup per listed site.  From the streamed fine state g (before
+// its collision) of the site: the fine collision with its face fluxes F,
+// the coarse face fluxes they imply under the restriction R
+// (div_c G = R div F: coarse face k takes the fine faces 4k-2 and 4k-1 on
+// either side of the shared fine cell 4k-2, (F_{4k-2} + F_{4k-1}) / 8 per
+// fine line, lines combined with R across the other axis), minus the face
+// fluxes of the coarse collision of R g: the target fluxes T with
+// pred - div T = R (C_f g), pred = C_c (R g).  Features and weights from
+// pred, as in k_flux_samples.
+template <int NVF, int NVC>
+__global__ __launch_bounds__(256) void k_flux_samples_nat(
+    CoarseGeom g, CollideCoef cf, CollideCoef cc, float alpha_f,
+    float alpha_c, const float* __restrict__ ff, const float* __restrict__ fp,
+    const float* __restrict__ u, const int32_t* __restrict__ sites,
+    float* __restrict__ X, float* __restrict__ T, float* __restrict__ Wt) {
+  static_assert(NVF == 4 * (NVC - 1) + 1, "stride-4 lattices");
+  constexpr int NFF = NVF * (NVF + 1), NFC = NVC * (NVC + 1);
+  constexpr int NFACE = 2 * NVC * (NVC - 1);
+  __shared__ float c[NVF * NVF], tmp[NFF], Fx[NFF], Fy[NFF];
+  __shared__ float rc[NVC * NVC], pred[NVC * NVC];
+  __shared__ float tx[NVC * (NVC + 1)], ty[(NVC + 1) * NVC];
+  __shared__ float msite;
+  const int tid = (int)threadIdx.x, bd = (int)blockDim.x;
+  const int64_t S = (int64_t)g.nx * g.ny;
+  const int site = sites[blockIdx.x];
+  const float ux = u[site], uy = u[S + site];
+  for (int i = tid; i < NVF * NVF; i += bd) c[i] = ff[(size_t)i * S + site];
+  for (int i = tid; i < NVC * NVC; i += bd) pred[i] = fp[(size_t)i * S + site];
+  __syncthreads();
+  // R g (before the fine collision changes c)
+  for (int q = tid; q < NVC * NVC; q += bd) {
+    const int Jy = q / NVC, Jx = q - Jy * NVC;
+    float acc = 0.f;
+    for (int oy = -2; oy <= 2; ++oy) {
+      const int jy = 4 * Jy + oy;
+      if (jy < 0 || jy >= NVF) continue;
+      for (int ox = -2; ox <= 2; ++ox) {
+        const int jx = 4 * Jx + ox;
+        if (jx < 0 || jx >= NVF) continue;
+        acc += rweight(oy) * rweight(ox) * c[jy * NVF + jx];
+      }
+    }
+    rc[q] = acc;
+  }
+  if (tid == 0) {  // site mass of pred, in a fixed order
+    float m = 0.f;
+    for (int i = 0; i < NVC * NVC; ++i) m += pred[i];
+    msite = m;
+  }
+  CollideCoef pf = cf;
+  pf.ax = ux * alpha_f;
+  pf.ay = uy * alpha_f;
+  collide_record<NVF>(c, tmp, Fx, Fy, pf);
+  // natural coarse fluxes of the fine collision
+  for (int q = tid; q < NFC; q += bd) {
+    const int a = q / (NVC + 1), k = q - a * (NVC + 1);  // line a, face k
+    float gx = 0.f, gy = 0.f;
+    if (k >= 1 && k <= NVC - 1) {
+      for (int o = -2; o <= 2; ++o) {
+        const int j = 4 * a + o;
+        if (j < 0 || j >= NVF) continue;
+        const float wgt = rweight(o) * 0.125f;
+        gx += wgt * (Fx[j * (NVF + 1) + 4 * k - 2] + Fx[j * (NVF + 1) + 4 * k - 1]);
+        gy += wgt * (Fy[(4 * k - 2) * NVF + j] + Fy[(4 * k - 1) * NVF + j]);
+      }
+    }
+    tx[a * (NVC + 1) + k] = gx;  // x-faces of row a
+    ty[k * NVC + a] = gy;        // y-faces of column a
+  }
+  __syncthreads();
+  // minus the coarse collision's own fluxes (Fx, Fy and tmp reused)
+  CollideCoef pc = cc;
+  pc.ax = ux * alpha_c;
+  pc.ay = uy * alpha_c;
+  collide_record<NVC>(rc, tmp, Fx, Fy, pc);
+  const size_t base = (size_t)blockIdx.x * NFACE;
+  for (int f = tid; f < NFACE; f += bd) {
+    float st[5], ms, sg, anu, G;
+    if (f < NVC * (NVC - 1)) {  // x-face (row jy, face k)
+      const int jy = f / (NVC - 1), k = f - jy * (NVC - 1) + 1;
+      auto line = [&](int cc2) { return pred[jy * NVC + cc2]; };
+      face_feat(line, NVC, k, ux, g, st, &ms, &sg, &anu);
+      G = tx[jy * (NVC + 1) + k] - Fx[jy * (NVC + 1) + k];
+    } else {  // y-face (face k, column jx)
+      const int q = f - NVC * (NVC - 1);
+      const int k = q / NVC + 1, jx = q - (k - 1) * NVC;
+      auto line = [&](int cc2) { return pred[cc2 * NVC + jx]; };
+      face_feat(line, NVC, k, uy, g, st, &ms, &sg, &anu);
+      G = ty[k * NVC + jx] - Fy[k * NVC + jx];
+    }
     const bool use = ms > kMinStencilMass && ms >= g.line_eps * msite;
     const float inv = use ? 1.0f / ms : 0.f;
     float* x = X + (base + f) * kNF;
@@ -652,6 +830,20 @@ hipError_t launch_flux_samples(const CoarseGeom& g, const float* f_pred,
   if (g.nv != kNVC || nsites < 1) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_flux_samples<kNVC>, dim3(nsites), dim3(320), 0, s, g,
                      f_pred, f_true, u, sites, X, t, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_flux_samples_natural(
+    const CoarseGeom& g, const NaturalCoef& nc, const float* f_fine,
+    const float* f_pred, const float* u, const int32_t* sites, int nsites,
+    float* X, float* t, float* w, hipStream_t s) {
+  if (g.nv != kNVC || nc.nv_fine != 4 * (kNVC - 1) + 1 || nsites < 1)
+    return hipErrorInvalidValue;
+  CollideCoef cf{0.f, 0.f, nc.beta_f, nc.D_f, nc.nsub_f, nc.koren_f};
+  CollideCoef cc{0.f, 0.f, nc.beta_c, nc.D_c, nc.nsub_c, nc.koren_c};
+  hipLaunchKernelGGL((k_flux_samples_nat<4 * (kNVC - 1) + 1, kNVC>),
+                     dim3(nsites), dim3(256), 0, s, g, cf, cc, nc.alpha_f,
+                     nc.alpha_c, f_fine, f_pred, u, sites, X, t, w);
   return hipGetLastError();
 }
 

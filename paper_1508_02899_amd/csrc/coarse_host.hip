@@ -155,6 +155,54 @@ int lattice_mlp_samples(lattice_t* L, double dt, double tau_p, double St,
   return LATTICE_OK;
 }
 
+int lattice_mlp_samples_natural(const lattice_t* fine, lattice_t* L,
+                                double dt, double tau_p, double kappa,
+                                double St, double rel_eps,
+                                const float* f_fine, const float* f_pred,
+                                const float* u, const int32_t* sites,
+                                int64_t nsites, float* X, float* t, float* w) {
+  if (!fine || !L || !f_fine || !f_pred || !u || !sites || !X || !t || !w ||
+      nsites < 1 || nsites > (1 << 30) || !(dt > 0) || !isfinite(dt) ||
+      !(tau_p > 0) || !isfinite(tau_p) || !(kappa >= 0) ||
+      !isfinite(kappa) || !(St > 0) || !(rel_eps >= 0) || !(rel_eps < 1))
+    return LATTICE_EINVAL;
+  const lattice_desc& d = L->d;
+  const lattice_desc& e = fine->d;
+  if (d.dim != 2 || d.nv != 17 || d.dtype != LATTICE_F32 || e.dim != 2 ||
+      e.nv != 65 || e.dtype != LATTICE_F32)
+    return LATTICE_ENOTSUP;
+  if (e.nx != d.nx || e.ny != d.ny || e.dx != d.dx ||
+      d.vstride != 4 * e.vstride)
+    return LATTICE_EINVAL;  // not the stride-4 coarse lattice of `fine`
+  const double dvc = d.vstride * d.dx / dt, dvf = e.vstride * e.dx / dt;
+  lat::CoarseGeom g;
+  g.nx = (int)d.nx;
+  g.ny = (int)d.ny;
+  g.nv = d.nv;
+  g.dv = (float)dvc;
+  g.nu_scale = (float)(dt / (tau_p * dvc));
+  g.log_st = (float)log(St);
+  g.line_eps = (float)rel_eps;
+  lat::NaturalCoef nc;
+  nc.nv_fine = e.nv;
+  const double dtf = dt / e.nsub, dtc = dt / d.nsub;
+  nc.alpha_f = (float)(dtf / (dvf * tau_p));
+  nc.beta_f = (float)(dtf / tau_p);
+  nc.D_f = (float)(kappa * dtf / (dvf * dvf));
+  nc.nsub_f = e.nsub;
+  nc.koren_f = e.scheme == LATTICE_KOREN;
+  nc.alpha_c = (float)(dtc / (dvc * tau_p));
+  nc.beta_c = (float)(dtc / tau_p);
+  nc.D_c = (float)(kappa * dtc / (dvc * dvc));
+  nc.nsub_c = d.nsub;
+  nc.koren_c = d.scheme == LATTICE_KOREN;
+  if (lat::launch_flux_samples_natural(g, nc, f_fine, f_pred, u, sites,
+                                       (int)nsites, X, t, w,
+                                       L->stream) != hipSuccess)
+    return LATTICE_EHIP;
+  return LATTICE_OK;
+}
+
 int lattice_mlp_grad(lattice_mlp_t* M, const float* X, const float* t,
                      const float* w, int64_t n, float* grad, double* loss) {
   if (!M || !X || !t || !w || n < 1) return LATTICE_EINVAL;

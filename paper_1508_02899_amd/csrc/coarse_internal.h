@@ -40,6 +40,29 @@ hipError_t launch_flux_samples(const CoarseGeom& g, const float* f_pred,
                                const int32_t* sites, int nsites, float* X,
                                float* t, float* w, hipStream_t s);
 
+// Collision coefficients of a fine lattice and of its stride-4 coarse
+// lattice for the natural-flux training targets: alpha = dt_s / (dv tau_p)
+// (times u: drift of the zero-velocity cell), beta = dt_s / tau_p,
+// D = kappa dt_s / dv^2, nsub sub-steps, Koren (1) or upwind (0).
+struct NaturalCoef {
+  int nv_fine;
+  float alpha_f, beta_f, D_f;
+  int nsub_f, koren_f;
+  float alpha_c, beta_c, D_c;
+  int nsub_c, koren_c;
+};
+
+// Training samples with natural targets: from the streamed fine state
+// f_fine (before its collision; [nv_f^2][ny][nx]) and pred = the coarse
+// collision of its restriction ([nv_c^2][ny][nx]), per listed site and
+// interior coarse face: the coarse fluxes implied by the fine collision's
+// face fluxes under the restriction, minus the coarse collision's fluxes.
+// Same outputs as launch_flux_samples.
+hipError_t launch_flux_samples_natural(
+    const CoarseGeom& g, const NaturalCoef& nc, const float* f_fine,
+    const float* f_pred, const float* u, const int32_t* sites, int nsites,
+    float* X, float* t, float* w, hipStream_t s);
+
 // Per-block partial gradients of the weighted squared loss over n samples
 // (nblocks rows of kNParams + 1 floats: gradient, then the block's loss sum).
 hipError_t launch_mlp_grad(const float* params, const float* X,

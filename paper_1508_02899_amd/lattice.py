@@ -35,7 +35,8 @@ EXPORTS = (
     "lattice_batch_sync", "lattice_batch_destroy", "lattice_batch_last_error",
     "lattice_restrict",
     "lattice_mlp_create", "lattice_mlp_set_params", "lattice_mlp_get_params",
-    "lattice_mlp_samples", "lattice_mlp_grad", "lattice_mlp_train",
+    "lattice_mlp_samples", "lattice_mlp_samples_natural", "lattice_mlp_grad",
+    "lattice_mlp_train",
     "lattice_mlp_forward", "lattice_mlp_attach", "lattice_mlp_destroy",
 )
 
@@ -154,6 +155,8 @@ def load_library(path: str = LIB_PATH):
     L.lattice_mlp_get_params.argtypes = [vp, pf]
     L.lattice_mlp_samples.argtypes = [vp, dbl, dbl, dbl, dbl, vp, vp, vp, vp,
                                       i64, vp, vp, vp]
+    L.lattice_mlp_samples_natural.argtypes = [vp, vp, dbl, dbl, dbl, dbl, dbl,
+                                              vp, vp, vp, vp, i64, vp, vp, vp]
     L.lattice_mlp_grad.argtypes = [vp, vp, vp, vp, i64, vp,
                                    ctypes.POINTER(dbl)]
     L.lattice_mlp_train.argtypes = [vp, vp, vp, vp, i64, i64, i64, dbl,
@@ -631,6 +634,23 @@ class Mlp:
             _ptr(f_pred),
             _ptr(f_true), _ptr(u), _ptr(sites), sites.numel(), _ptr(X),
             _ptr(t), _ptr(w)))
+        return X, t, w
+
+    def samples_natural(self, fine, lat, dt, tau_p, kappa, St, f_fine,
+                        f_pred, u, sites, rel_eps: float = 0.0):
+        """Training samples with natural flux targets at the given sites:
+        f_fine = the fine state after streaming (before its collision),
+        f_pred = the coarse collision of its restriction (lattice lat)."""
+        torch = _torch()
+        nf = 544
+        n = sites.numel() * nf
+        X = torch.empty((n, 8), dtype=torch.float32, device=f_pred.device)
+        t = torch.empty(n, dtype=torch.float32, device=f_pred.device)
+        w = torch.empty(n, dtype=torch.float32, device=f_pred.device)
+        self._check(self.lib.lattice_mlp_samples_natural(
+            fine._L, lat._L, float(dt), float(tau_p), float(kappa), float(St),
+            float(rel_eps), _ptr(f_fine), _ptr(f_pred), _ptr(u), _ptr(sites),
+            sites.numel(), _ptr(X), _ptr(t), _ptr(w)))
         return X, t, w
 
     def attach(self, lat, St: float, line_eps: float = 1e-4):

@@ -200,6 +200,68 @@ def test_flux_samples_match_oracle():
     lat.close()
 
 
+@pytest.mark.parametrize("scheme,nsf,nsc", [("koren", 3, 1),
+                                            ("upwind", 2, 2)])
+def test_natural_flux_samples_match_oracle(scheme, nsf, nsc):
+    """Natural flux targets: the fine collision of each listed site redone
+    with its face fluxes recorded, restricted to coarse faces, minus the
+    coarse collision's fluxes -- against the oracle's FP64 version from the
+    same streamed fine state; features and weights from the coarse
+    collision the library computed."""
+    import torch
+    from oracle import coarse as C
+    from paper_1508_02899_amd import Lattice, LatticeSpec, Mlp, restrict
+    rng = np.random.default_rng(41 + nsf)
+    n, nvf, nvc = 6, 65, 17
+    L = 2 * math.pi
+    dx = L / n
+    dvf = 3.0 / 32
+    dt = dx / dvf
+    tau_p, kappa, St = 400.0, 2e-4, 2.0  # coarse CFL ~0.3 at nsub 1
+    g = (rng.random((nvf * nvf, n, n)) ** 4).astype(np.float32)
+    u = (0.8 * np.tanh(rng.standard_normal((1, 2, n, n)))).astype(np.float32)
+    fs = LatticeSpec(dim=2, nx=n, ny=n, nv=nvf, dx=dx, scheme=scheme,
+                     nsub=nsf)
+    cs = LatticeSpec(dim=2, nx=n, ny=n, nv=nvc, dx=dx, vstride=4,
+                     scheme=scheme, nsub=nsc)
+    fine, coarse, m = Lattice(fs), Lattice(cs), Mlp()
+    gd = torch.from_numpy(g).cuda()
+    ud = torch.from_numpy(u).cuda()
+    fc = restrict(gd, 2)
+    coarse.collide(fc, ud, tau_p, kappa, dt, 1)
+    sites = np.array([0, 9, 35], dtype=np.int32)
+    X, t, w = m.samples_natural(fine, coarse, dt, tau_p, kappa, St, gd, fc,
+                                ud, torch.from_numpy(sites).cuda())
+    X, t, w = X.cpu().numpy(), t.cpu().numpy(), w.cpu().numpy()
+    pred_gpu = fc.cpu().numpy()
+    dvc = 4 * dvf
+    koren = scheme == "koren"
+    fine_c = dict(alpha_scale=(dt / nsf) / (dvf * tau_p), beta=(dt / nsf) / tau_p,
+                  D=kappa * (dt / nsf) / dvf ** 2, nsub=nsf, koren=koren)
+    coarse_c = dict(alpha_scale=(dt / nsc) / (dvc * tau_p),
+                    beta=(dt / nsc) / tau_p, D=kappa * (dt / nsc) / dvc ** 2,
+                    nsub=nsc, koren=koren)
+    for q, s_ in enumerate(sites):
+        y, x = divmod(int(s_), n)
+        ux, uy = float(u[0, 0, y, x]), float(u[0, 1, y, x])
+        T, pred, _ = C.natural_targets(g[:, y, x], ux, uy, fine_c, coarse_c)
+        # the oracle's coarse collision agrees with the library's
+        pg = pred_gpu[:, y, x].astype(np.float64)
+        assert rel_l2(pg, pred.reshape(-1)) < 1e-5
+        Xo, ms, sg = C.face_features(pg, nvc, ux, uy, dvc, dt, tau_p, St)
+        use = ms > 0
+        to = np.where(use, sg * T / np.where(use, ms, 1), 0)
+        sl = slice(q * 544, (q + 1) * 544)
+        np.testing.assert_allclose(X[sl], Xo, rtol=1e-5, atol=1e-6)
+        np.testing.assert_allclose(w[sl], ms, rtol=1e-5)
+        err = np.sqrt(np.sum(ms * (t[sl] - to) ** 2) / np.sum(ms * to ** 2))
+        say(f"  site {s_}: mass-weighted target rel L2 {err:.2e}")
+        assert err < 1e-3
+    m.close()
+    fine.close()
+    coarse.close()
+
+
 def test_correction_pass_matches_oracle_and_conserves_mass():
     """A coarse 2D step with the network attached vs plain step + the
     oracle's correction of every site."""

@@ -140,3 +140,76 @@ def test_face_features_hand_example():
     assert ms[ny0 + 1 * nv + 4] > 0      # column 4: row 0 holds 5
     assert ms[ny0 + 3 * nv + 4] == 0     # face 4 of column 4: cells 1..4 empty
     assert np.all(X[ny0 + 3 * nv + 4, :5] == 0)
+
+
+@pytest.mark.parametrize("nv,s,nsub,scheme", [(65, 1, 3, "koren"),
+                                              (17, 4, 2, "koren"),
+                                              (9, 1, 2, "upwind")])
+def test_collide_site_is_the_lattice_step_of_a_one_site_lattice(nv, s, nsub,
+                                                                scheme):
+    """On a 1 x 1 periodic lattice streaming is the identity, so a full
+    lattice step of the C oracle is the collision alone; the recorded face
+    fluxes reproduce the change exactly (c0 - div F = c1)."""
+    import oracle
+    rng = np.random.default_rng(nv + s)
+    c0 = rng.random((nv, nv)) ** 3
+    ux, uy = 0.7, -0.4
+    dx, dt, tau = 0.1, 0.05, 3.0
+    dv = s * dx / dt
+    kappa = 0.02 * dv * dv / dt
+    dts = dt / nsub
+    c1, Fx, Fy = C.collide_site(c0, ux, uy, dts / (dv * tau), dts / tau,
+                                kappa * dts / dv ** 2, nsub,
+                                scheme == "koren")
+    want = oracle.step(c0.reshape(nv * nv, 1, 1),
+                       np.array([ux, uy]).reshape(1, 2, 1, 1), dim=2, dx=dx,
+                       tau_p=tau, kappa=kappa, dt=dt, nsteps=1, scheme=scheme,
+                       s=s, nsub=nsub).reshape(nv, nv)
+    assert np.abs(c1 - want).max() <= 1e-14 * np.abs(want).max()
+    div = (Fx[:, 1:] - Fx[:, :-1]) + (Fy[1:, :] - Fy[:-1, :])
+    assert np.abs(c0 - div - c1).max() <= 1e-14 * np.abs(c0).max()
+    assert not Fx[:, 0].any() and not Fx[:, -1].any()
+    assert not Fy[0, :].any() and not Fy[-1, :].any()
+
+
+def test_natural_coarse_fluxes_carry_the_restricted_divergence():
+    """div_c G = R div F for any fine face fluxes (outer faces closed), and a
+    single fine flux phi through fine face 4k-1 or 4k-2 shows up as phi/8
+    through coarse face k (and 0 through the faces inside a coarse cell)."""
+    rng = np.random.default_rng(5)
+    nvf, nvc = 65, 17
+    Fx = rng.standard_normal((nvf, nvf + 1))
+    Fy = rng.standard_normal((nvf + 1, nvf))
+    Fx[:, 0] = Fx[:, -1] = 0.0
+    Fy[0, :] = Fy[-1, :] = 0.0
+    Gx, Gy = C.natural_coarse_fluxes(Fx, Fy)
+    divf = (Fx[:, 1:] - Fx[:, :-1]) + (Fy[1:, :] - Fy[:-1, :])
+    divc = (Gx[:, 1:] - Gx[:, :-1]) + (Gy[1:, :] - Gy[:-1, :])
+    Rdiv = C.restrict(divf.reshape(-1, 1), 2).reshape(nvc, nvc)
+    assert np.allclose(divc, Rdiv, rtol=0, atol=1e-13)
+    # 1D reading of the same map: one fine flux at a time, fine row 8 (a
+    # coarse-centred row, restriction weight 1/4 across the other axis)
+    for m, want in [(4 * 3 - 1, 1 / 8), (4 * 3 - 2, 1 / 8), (4 * 3, 0.0),
+                    (4 * 3 + 1, 0.0)]:
+        Fx = np.zeros((nvf, nvf + 1))
+        Fx[8, m] = 1.0
+        Gx, _ = C.natural_coarse_fluxes(Fx, np.zeros((nvf + 1, nvf)))
+        k = 3
+        assert Gx[2, k] == pytest.approx(want / 4.0)
+
+
+def test_natural_targets_close_the_coarse_step():
+    """pred - div T = R (fine collision of g): the targets map the coarse
+    collision of the restricted state onto the restricted fine collision."""
+    rng = np.random.default_rng(9)
+    g = rng.random(65 * 65) ** 4
+    dt, tau, kappa, dvf = 0.3, 4 * math.pi, 1e-4, 3.0 / 32
+    fine = dict(alpha_scale=(dt / 3) / (dvf * tau), beta=(dt / 3) / tau,
+                D=kappa * (dt / 3) / dvf ** 2, nsub=3, koren=True)
+    dvc = 4 * dvf
+    coarse = dict(alpha_scale=dt / (dvc * tau), beta=dt / tau,
+                  D=kappa * dt / dvc ** 2, nsub=1, koren=True)
+    T, pred, true = C.natural_targets(g, 0.6, -0.8, fine, coarse)
+    D = C.divergence_matrix(17)
+    assert np.abs(pred.reshape(-1) - D @ T - true.reshape(-1)).max() <= \
+        1e-15 * np.abs(true).max() * 100
