@@ -484,6 +484,9 @@ def main():
                     choices=sorted(WORKLOADS))
     ap.add_argument("--scheme", default="koren", choices=["koren", "upwind"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--st", type=float, default=None,
+                    help="Stokes number instead of the workload's own "
+                         "(tau_p = St L / u_rms)")
     ap.add_argument("--flow", default="prestaged",
                     choices=["prestaged", "device"],
                     help="device: synthesise the flow slices on the GPU from "
@@ -522,6 +525,10 @@ def main():
     from paper_1508_02899_amd import Lattice, LatticeSpec, inputs
 
     w = WORKLOADS[args.workload]
+    if args.st is not None:
+        if not args.st > 0:
+            sys.exit("--st must be > 0")
+        w = dict(w, St=args.st)
     if w.get("batch"):
         torch.cuda.set_device(0)
         return bench_batch(args, w)
