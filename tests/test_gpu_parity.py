@@ -123,6 +123,22 @@ def test_2d_f32_parity_nv65():
     assert err <= FP32_REL_L2
 
 
+@pytest.mark.parametrize("nx,ny,nv", [(1, 1, 9), (1, 5, 33), (7, 1, 17),
+                                      (3, 2, 33), (2, 3, 65), (1, 2, 5)])
+def test_2d_degenerate_lattices(nx, ny, nv):
+    """Lattices of one or a few sites per axis (every streaming shift wraps
+    several times; all but a few lanes of a workgroup are duplicates),
+    velocity stride 4 and two collision sub-steps."""
+    say(f"2d degenerate {nx}x{ny} nv={nv}")
+    f0, u, p = make_case(2, nx, nv, ny=ny, seed=600 + 7 * nx + ny + nv,
+                         slices=2, s=4, nsub=2)
+    got = run_gpu(f0, u, p, 4, u_hold=2)
+    want = run_oracle(f0, u, p, 4, u_hold=2)
+    err = rel_l2(got, want)
+    say("  rel L2", err)
+    assert err <= FP32_REL_L2
+
+
 @pytest.mark.parametrize("nv", [3, 5, 9, 17, 33])
 def test_2d_f64_parity(nv):
     say(f"2d f64 nv={nv}")
