@@ -232,9 +232,12 @@ struct OutStage {
 // sites per workgroup beat 64) at the cost of a barrier over more waves.
 template <typename T, int NV, int P>
 constexpr int step2d_wgw() {
-  // nv = 65 (17 cells per lane) needs more than the 256 registers a wave
-  // may hold at 8 waves per workgroup
-  return (P == 4 && sizeof(T) == 4 && NV <= 33) ? 8 : 4;
+  // FP32 lanes of 9 cells or fewer (nv <= 33 in 4 parts, nv = 65 in 8)
+  // fit 8 waves per workgroup; longer slices need more than the registers
+  // a wave may hold there
+  return sizeof(T) == 4 && ((P == 4 && NV <= 33) || (P == 8 && NV == 65))
+             ? 8
+             : 4;
 }
 
 // INTERIOR: every source site of the tile lies inside [0, nx) without
