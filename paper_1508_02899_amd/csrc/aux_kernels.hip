@@ -27,15 +27,50 @@ __device__ double block_sum(double v, double* sh) {
 }
 
 // One workgroup per velocity plane: sum of the plane's sites in FP64.
-// Thread t adds sites t, t+256, ... in order (coalesced), then the tree.
+// When the plane is 16-byte aligned and a whole number of 16-byte pieces,
+// thread t adds pieces t, t+256, ... (coalesced 16-byte loads, one FP64
+// partial sum per element of a piece, combined in a fixed order);
+// otherwise sites t, t+256, ... one by one.  Then the tree.  The order of
+// the additions depends only on the plane size, so repeated calls give the
+// same bits.
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  typedef float4 type;
+  static constexpr int n = 4;
+};
+template <>
+struct Vec16<double> {
+  typedef double2 type;
+  static constexpr int n = 2;
+};
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_plane_sums(const T* __restrict__ f,
                                                        int64_t sites,
                                                        double* __restrict__ out) {
   __shared__ double sh[kBlock];
+  using V = typename Vec16<T>::type;
+  constexpr int NE = Vec16<T>::n;
   const T* p = f + (size_t)blockIdx.x * (size_t)sites;
   double acc = 0.0;
-  for (int64_t i = threadIdx.x; i < sites; i += kBlock) acc += (double)p[i];
+  if (sites % NE == 0 && ((uintptr_t)p & 15) == 0) {  // uniform
+    const V* q = reinterpret_cast<const V*>(p);
+    const int64_t n = sites / NE;
+    double a[NE] = {};
+#pragma unroll 4
+    for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+      const V v = q[i];
+      const T* e = reinterpret_cast<const T*>(&v);
+#pragma unroll
+      for (int k = 0; k < NE; ++k) a[k] += (double)e[k];
+    }
+#pragma unroll
+    for (int k = 0; k < NE; ++k) acc += a[k];
+  } else {
+    for (int64_t i = threadIdx.x; i < sites; i += kBlock) acc += (double)p[i];
+  }
   const double s = block_sum(acc, sh);
   if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
