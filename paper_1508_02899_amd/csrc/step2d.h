@@ -336,6 +336,10 @@ __device__ __forceinline__ void step2d_tile(
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
     __builtin_amdgcn_s_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    // the staged row leaves at raised wave priority: the workgroup's waves
+    // issue their stores ahead of the neighbouring workgroups' arithmetic
+    // (measured: about 1 % shorter passes)
+    __builtin_amdgcn_s_setprio(3);
     const T* sb = stage + (t & 1) * O::SIZE + fj0 * O::STRIDE + fs;
     T* orow = frow0 + (size_t)(t - 3) * rowpitch;
     constexpr int KL = O::K - 1;  // the last round covers planes < NV only
@@ -347,6 +351,7 @@ __device__ __forceinline__ void step2d_tile(
 #pragma unroll
     for (int k = 0; k < KL; ++k)
       row_store(orow, (uint32_t)(k * P) * slot_bytes, flane, v[k]);
+    __builtin_amdgcn_s_setprio(0);
     row_store_if(orow, (uint32_t)(KL * P) * slot_bytes, flane, v[KL],
                  last_in);
   };
