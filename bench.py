@@ -242,13 +242,18 @@ def bench_coarse(args, w):
         fn.all = u
         return fn
 
-    flow_a = flow(inputs.seed_for(5, 1), T_spin + T_train)
-    flow_b = flow(inputs.seed_for(5, 2), max(T_eval, W + K))
+    T_cal = 150
+    flow_a = flow(inputs.seed_for(5, 1), T_spin + T_train)   # training
+    flow_b = flow(inputs.seed_for(5, 2), max(T_eval, W + K))  # evaluation
+    # the output scale is calibrated under the training flow (from a fresh
+    # state), never under the evaluation flow
+    flow_c = flow_a
+    flows = (flow_a, flow_b)
     fs = LatticeSpec(dim=2, nx=n, ny=n, nv=nvf, dx=dx)
-    nsf = max(CC.nsub_for(fs, f.all, tau_p, kappa, dt) for f in (flow_a, flow_b))
+    nsf = max(CC.nsub_for(fs, f.all, tau_p, kappa, dt) for f in flows)
     fs = LatticeSpec(dim=2, nx=n, ny=n, nv=nvf, dx=dx, nsub=nsf)
     cs = CC.coarse_spec(fs)
-    nsc = max(CC.nsub_for(cs, f.all, tau_p, kappa, dt) for f in (flow_a, flow_b))
+    nsc = max(CC.nsub_for(cs, f.all, tau_p, kappa, dt) for f in flows)
     cs = CC.coarse_spec(fs, nsc)
     log(f"bench: coarse workload, fine nsub {nsf}, coarse nsub {nsc}")
     fine, coarse, mlp = Lattice(fs), Lattice(cs), Mlp()
@@ -264,6 +269,11 @@ def bench_coarse(args, w):
         loss = mlp.train(X, t, wt, batch=8192, steps=9000, lr=lr)
     del X, t, wt
     log(f"bench: network trained, last minibatch loss {loss:.3e}")
+    f0 = torch.from_numpy(inputs.gaussian_ic(2, n, nvf, dx, dv, ny=n)).cuda()
+    scale, cal = CC.calibrate_output_scale(fine, cs, mlp, St, f0, flow_c,
+                                           steps=T_cal, dt=dt, tau_p=tau_p,
+                                           kappa=kappa)
+    log(f"bench: output scale {scale} (calibration variance errors {cal})")
 
     plain, corr = Lattice(cs), Lattice(cs)
     mlp.attach(corr, St, 1e-3)
@@ -327,6 +337,9 @@ def bench_coarse(args, w):
             "ms_per_step_coarse_plain": round(ms_plain, 5),
             "ms_per_step_coarse_mlp": round(ms_mlp, 5),
             "speedup_vs_fine": round(ms_fine / ms_mlp, 3),
+            "output_scale": scale,
+            "calibration_variance_errors": {str(k): round(v, 5)
+                                            for k, v in cal.items()},
             "errors_vs_restricted_fine": err_r,
             "errors_vs_fine": err_f,
         },

@@ -178,6 +178,47 @@ def compare(fine: Lattice, coarse_runs: dict, f0_fine, flow, *, steps: int,
     return tracks, f, states
 
 
+def calibrate_output_scale(fine: Lattice, coarse_spec: LatticeSpec, mlp: Mlp,
+                           St: float, f0_fine, flow, *, steps: int, dt: float,
+                           tau_p: float, kappa: float, line_eps: float = 1e-3,
+                           scales=(1.0, 1.25, 1.5, 2.0, 2.5, 3.0),
+                           from_step: int = 50, every: int = 25):
+    """A-posteriori calibration of the trained network's output scale: the
+    coarse lattice runs once per candidate scale c (correction c * G; c is
+    folded into the output layer w3, b3) beside the fine lattice, from
+    f0_fine under ``flow`` (the training flow, or any flow other than the
+    one the model is evaluated on, within the lattices' CFL bounds), and
+    the scale with the smallest mean velocity-variance error against the
+    restricted fine state (steps >= from_step) is written into ``mlp``.
+    Returns (best scale, {scale: error})."""
+    import numpy as np
+    P0 = np.asarray(mlp.get_params(), dtype=np.float32)
+    nets, runs = {}, {}
+    for c in scales:
+        m = Mlp()
+        P = P0.copy()
+        P[-65:] *= c          # w3[64] and b3, the last 65 parameters
+        m.set_params(P)
+        lat = Lattice(coarse_spec)
+        m.attach(lat, St, line_eps)
+        nets[c], runs[f"s{c}"] = m, lat
+    levels = 1
+    tracks, _, _ = compare(fine, runs, f0_fine, flow, steps=steps, dt=dt,
+                           tau_p=tau_p, kappa=kappa, levels=levels,
+                           every=every)
+    err = errors({k: v for k, v in tracks.items() if k != "fine"}, "fine_R",
+                 coarse_spec.dx, from_step=from_step)
+    scores = {c: err[f"s{c}"]["variance"] for c in scales}
+    best = min(scores, key=scores.get)
+    P = P0.copy()
+    P[-65:] *= best
+    mlp.set_params(P)
+    for c in scales:
+        runs[f"s{c}"].close()
+        nets[c].close()
+    return best, scores
+
+
 def errors(tracks: dict, ref: str, dx: float, from_step: int = 0):
     """Per run: mean relative error of the velocity variance and the mean
     distance-averaged relative error of <rho_r^2> against the reference

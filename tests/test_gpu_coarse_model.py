@@ -1,6 +1,7 @@
 """The coarse velocity lattice with its learned face-flux correction
 against the fine lattice: training from fine runs and a side-by-side run
-under an unseen flow (the a-priori trained correction must beat the plain
+under an unseen flow (the a-priori trained correction, with its output
+scale calibrated a posteriori under the training flow, must beat the plain
 coarse lattice).  2D, 128^2 sites, fine 65^2 velocities, coarse 17^2
 (stride 4), St = 2, Koren."""
 import math
@@ -23,7 +24,7 @@ def test_learned_correction_beats_plain_coarse_lattice():
     dvf = V / ((nvf - 1) // 2)
     dt = dx / dvf
     tau, kappa = St * L, 1e-4
-    T_spin, T_train, T_eval = 100, 150, 300
+    T_spin, T_train, T_eval, T_cal = 100, 150, 300, 150
 
     def flow(seed, nsl):
         u = torch.from_numpy(inputs.flow2d_streamfunction(
@@ -34,11 +35,13 @@ def test_learned_correction_beats_plain_coarse_lattice():
 
     flow_a = flow(inputs.seed_for(5, 1), T_spin + T_train)
     flow_b = flow(inputs.seed_for(5, 2), T_eval)
+    flow_c = flow_a  # calibration: the training flow from a fresh state
+    flows = (flow_a, flow_b)
     fs = LatticeSpec(dim=2, nx=n, ny=n, nv=nvf, dx=dx)
-    nsf = max(CC.nsub_for(fs, fl.all, tau, kappa, dt) for fl in (flow_a, flow_b))
+    nsf = max(CC.nsub_for(fs, fl.all, tau, kappa, dt) for fl in flows)
     fs = LatticeSpec(dim=2, nx=n, ny=n, nv=nvf, dx=dx, nsub=nsf)
     cs = CC.coarse_spec(fs)
-    nsc = max(CC.nsub_for(cs, fl.all, tau, kappa, dt) for fl in (flow_a, flow_b))
+    nsc = max(CC.nsub_for(cs, fl.all, tau, kappa, dt) for fl in flows)
     cs = CC.coarse_spec(fs, nsc)
     fine, coarse, mlp = Lattice(fs), Lattice(cs), Mlp()
     mlp.set_params(CC.initial_params(5))
@@ -57,6 +60,13 @@ def test_learned_correction_beats_plain_coarse_lattice():
     l1, _ = mlp.grad(X, t, w)
     say(f"  training loss {l0:.3e} -> {l1:.3e}")
     assert l1 < 0.8 * l0
+    # output scale chosen a posteriori under the training flow
+    f0c = torch.from_numpy(inputs.gaussian_ic(2, n, nvf, dx, dvf, ny=n)).cuda()
+    scale, cal = CC.calibrate_output_scale(fine, cs, mlp, St, f0c, flow_c,
+                                           steps=T_cal, dt=dt, tau_p=tau,
+                                           kappa=kappa)
+    say(f"  output scale {scale}: calibration variance errors {cal}")
+    assert cal[scale] <= cal[1.0]
 
     plain, corr = Lattice(cs), Lattice(cs)
     mlp.attach(corr, St, 1e-3)
