@@ -265,8 +265,13 @@ def bench_coarse(args, w):
                                   dt=dt, tau_p=tau_p, kappa=kappa, St=St,
                                   sites_per_step=768, seed=1,
                                   first_step=T_spin)
+    n_samples = int(t.numel())
+    torch.cuda.synchronize()
+    t_train = time.perf_counter()
     for lr in (3e-3, 1e-3, 3e-4):
         loss = mlp.train(X, t, wt, batch=8192, steps=9000, lr=lr)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t_train
     del X, t, wt
     log(f"bench: network trained, last minibatch loss {loss:.3e}")
     f0 = torch.from_numpy(inputs.gaussian_ic(2, n, nvf, dx, dv, ny=n)).cuda()
@@ -337,6 +342,9 @@ def bench_coarse(args, w):
             "ms_per_step_coarse_plain": round(ms_plain, 5),
             "ms_per_step_coarse_mlp": round(ms_mlp, 5),
             "speedup_vs_fine": round(ms_fine / ms_mlp, 3),
+            "training": {"samples": n_samples, "adam_steps": 27000,
+                         "batch": 8192, "seconds": round(t_train, 3),
+                         "samples_per_s": round(27000 * 8192 / t_train)},
             "output_scale": scale,
             "calibration_variance_errors": {str(k): round(v, 5)
                                             for k, v in cal.items()},
