@@ -46,6 +46,12 @@ WORKLOADS = {
     # every 50 steps, FP32, batched persistent kernels replayed as a graph
     "batch-256x1d": dict(dim=1, n=0, nv=0, s=1, dtype="f32", St=0.0,
                          kappa=1e-4, vmax=0.0, batch=256),
+    # configuration 2 as run: its three Stokes numbers (0.1, 1, 10; Vmax 9,
+    # 2, 1) advanced together as one batch of three 16384 x 129 lattices,
+    # each with its own 32-mode OU flow, a new slice every step
+    "1d-16384-v129-3st": dict(dim=1, n=16384, nv=129, s=1, dtype="f32",
+                              St=1.0, kappa=1e-4, vmax=2.0, batch=3,
+                              st_set=((0.1, 9.0), (1.0, 2.0), (10.0, 1.0))),
     # 2D 256^2 sites: fine 65^2 velocities vs the stride-4 coarse 17^2
     # lattice with the learned face-flux correction (trained before timing
     # on samples of a fine run under another flow realization), St = 2
@@ -167,6 +173,26 @@ def batch_members(count, nsteps):
     return mems, states, flows
 
 
+def st_set_members(w, nsteps):
+    """The lattices of one 1D workload at several (St, Vmax): own dt, tau_p
+    and 32-mode OU flow each, one flow slice per step."""
+    from paper_1508_02899_amd import Member, inputs
+    L = 2 * math.pi
+    nx, nv = w["n"], w["nv"]
+    dx = L / nx
+    mems, states, flows = [], [], []
+    for r, (St, vmax) in enumerate(w["st_set"]):
+        dv = vmax / ((nv - 1) // 2)
+        dt = dx / dv
+        mems.append(Member(nx=nx, nv=nv, dx=dx, dt=dt, tau_p=St * L,
+                           kappa=w["kappa"], u_hold=1, n_u_slices=nsteps))
+        states.append(inputs.gaussian_ic(1, nx, nv, dx, dv))
+        flows.append(inputs.flow1d(nx, L, nsteps, modes=32,
+                                   spectrum="k-5/3", tau_f=1.0, dt=dt,
+                                   seed=inputs.seed_for(2, r))[:, 0])
+    return mems, states, flows
+
+
 def bench_batch(args, w):
     import numpy as np
     import torch
@@ -174,7 +200,10 @@ def bench_batch(args, w):
     from paper_1508_02899_amd import Batch
     from paper_1508_02899_amd.autotune import tune_batch
     K, W = args.steps, args.warmup
-    mems, states, flows = batch_members(w["batch"], W + K)
+    if w.get("st_set"):
+        mems, states, flows = st_set_members(w, W + K)
+    else:
+        mems, states, flows = batch_members(w["batch"], W + K)
     b = Batch(mems, scheme=args.scheme)
     chosen = tune_batch(b, flows, scheme=args.scheme, log=log)
     log(f"bench: batch tuning {chosen}")
@@ -207,11 +236,18 @@ def bench_batch(args, w):
         "ms_per_step": round(ms / K, 5), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": (f"batch-256x1d: {w['batch']} independent 1D "
-                                "realizations, nx~U[512,8192], nv in "
-                                "{33,65,129}, St log-uniform [0.1,10], own "
-                                "8-mode flow renewed every 50 steps, "
-                                f"{args.scheme}, graph of {G} steps"),
+        "config": {"workload": (
+                       f"{args.workload}: three 1D periodic lattices of "
+                       f"{w['n']} sites x {w['nv']} velocities (St, Vmax) = "
+                       f"{w['st_set']}, kappa={w['kappa']}, own 32-mode OU "
+                       f"flow each (a new slice every step), {args.scheme}, "
+                       f"advanced together as one batch, graph of {G} steps"
+                       if w.get("st_set") else
+                       f"batch-256x1d: {w['batch']} independent 1D "
+                       "realizations, nx~U[512,8192], nv in "
+                       "{33,65,129}, St log-uniform [0.1,10], own "
+                       "8-mode flow renewed every 50 steps, "
+                       f"{args.scheme}, graph of {G} steps"),
                    "cells": cells, "mass_drift_rel_max": drift,
                    "tuning": {str(k): v for k, v in chosen.items()}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1),

@@ -298,8 +298,9 @@ typedef struct {
   int64_t n_u_slices;  /* slices stored for this member (>= 1) */
 } lattice_member_desc;
 
-/* Validate count members (all must satisfy Eq. 4 and have Vmax alone
- * within the drift bound) and allocate the packed scratch state, the
+/* Validate count members (1 <= count <= 65535; all must satisfy Eq. 4 and
+ * have Vmax alone within the drift bound) and allocate the packed scratch
+ * state, the
  * member table, the work lists and reduction buffers.  EINVAL, EDIFF, ECFL,
  * ENOMEM, EHIP.  scheme: LATTICE_UPWIND / LATTICE_KOREN; stream: hipStream_t
  * or NULL. */

@@ -118,21 +118,24 @@ __global__ __launch_bounds__(parts_threads<NV>()) void k_batch1d_parts(
 }
 
 // Per member: flag |= 1 if one of the slices the call uses has |u| past the
-// member's drift bound or non-finite.  One workgroup per member.
+// member's drift bound or non-finite.  Grid (chunks, members): the
+// workgroups of one member share its slices grid-stride.
 __global__ __launch_bounds__(256) void k_batch_cfl(
     const float* __restrict__ u, const BatchMember* __restrict__ mem,
     int64_t nsteps, int strict, int* __restrict__ mflag) {
-  const BatchMember m = mem[blockIdx.x];
+  const BatchMember m = mem[blockIdx.y];
   if (!(m.umax_ok < 3.0e38f)) return;  // no drag: no drift bound
   const int64_t need = m.u_hold > 0 ? (nsteps + m.u_hold - 1) / m.u_hold : 1;
   const int64_t n = need * m.nx;
   bool bad = false;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
     float a = u[m.u_off + i];
     a = a < 0.f ? -a : a;
     bad |= strict ? !(a < m.umax_ok) : !(a <= m.umax_ok);
   }
-  if (__any(bad) && ((int)threadIdx.x & 63) == 0) atomicOr(&mflag[blockIdx.x], 1);
+  if (__any(bad) && ((int)threadIdx.x & 63) == 0)
+    atomicOr(&mflag[blockIdx.y], 1);
 }
 
 // FP64 sum of one velocity plane of one member per workgroup.
@@ -253,10 +256,15 @@ hipError_t launch_batch1d(const BatchLaunch& a, hipStream_t s) {
 }
 
 hipError_t launch_batch_cfl(const float* u, const BatchMember* mem, int count,
-                            int64_t nsteps, int strict, int* mflag,
-                            hipStream_t s) {
-  hipLaunchKernelGGL(k_batch_cfl, dim3(count), dim3(256), 0, s, u, mem, nsteps,
-                     strict, mflag);
+                            int64_t nsteps, int64_t max_values, int strict,
+                            int* mflag, hipStream_t s) {
+  if (count < 1 || count > 65535) return hipErrorInvalidValue;
+  // about 16 values per thread for the largest member, at most 4096
+  // workgroups per member
+  int64_t chunks = (max_values + 256 * 16 - 1) / (256 * 16);
+  chunks = chunks < 1 ? 1 : (chunks > 4096 ? 4096 : chunks);
+  hipLaunchKernelGGL(k_batch_cfl, dim3((unsigned)chunks, (unsigned)count),
+                     dim3(256), 0, s, u, mem, nsteps, strict, mflag);
   return hipGetLastError();
 }
 

@@ -173,7 +173,7 @@ int lattice_batch_init(const lattice_member_desc* members, int32_t count,
                        lattice_batch_t** out) {
   if (!out) return LATTICE_EINVAL;
   *out = nullptr;
-  if (!members || count < 1 || vstride < 1 ||
+  if (!members || count < 1 || count > 65535 || vstride < 1 ||
       (scheme != LATTICE_UPWIND && scheme != LATTICE_KOREN))
     return LATTICE_EINVAL;
   lattice_batch_t* B = new (std::nothrow) lattice_batch;
@@ -375,7 +375,13 @@ int lattice_batch_step(lattice_batch_t* B, float* f, const float* u,
                   (long long)d.n_u_slices, (long long)need);
   }
   if (nsteps == 0) return LATTICE_OK;
-  BCHK(B, lat::launch_batch_cfl(u, B->d_mem, B->count, nsteps,
+  int64_t max_values = 1;
+  for (int r = 0; r < B->count; ++r) {
+    const lattice_member_desc& d = B->desc[r];
+    const int64_t need = d.u_hold > 0 ? (nsteps + d.u_hold - 1) / d.u_hold : 1;
+    if (need * d.nx > max_values) max_values = need * d.nx;
+  }
+  BCHK(B, lat::launch_batch_cfl(u, B->d_mem, B->count, nsteps, max_values,
                                 B->scheme == LATTICE_UPWIND, B->d_flag,
                                 B->stream));
   BCHK(B, lat::launch_set_int(B->d_base, 0, B->stream));

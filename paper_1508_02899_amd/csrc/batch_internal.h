@@ -55,9 +55,11 @@ hipError_t launch_batch1d(const BatchLaunch& a, hipStream_t s);
 // Sites per split-column tile of a capacity class (0: no split-column
 // kernel for it).
 int batch_parts_sites(int cap);
+// max_values: the largest number of flow values one member's check reads
+// (slices used x nx), to size the grid.
 hipError_t launch_batch_cfl(const float* u, const BatchMember* mem, int count,
-                            int64_t nsteps, int strict, int* mflag,
-                            hipStream_t s);
+                            int64_t nsteps, int64_t max_values, int strict,
+                            int* mflag, hipStream_t s);
 hipError_t launch_batch_moments(const float* f, const BatchPlane* planes,
                                 int nplanes, const BatchMember* mem, int count,
                                 double* plane_sums, double* out,

@@ -190,6 +190,33 @@ def test_batch_freezes_only_the_violating_member():
     b.close()
 
 
+def test_batch_flow_check_reaches_the_last_slice():
+    """A new flow slice every step and many steps: the check of a member's
+    slices is spread over many workgroups; one value past the drift bound
+    in the very last slice still freezes exactly that member."""
+    import torch
+    from paper_1508_02899_amd import Batch
+    from paper_1508_02899_amd.lattice import ECFL
+    rng = np.random.default_rng(25)
+    nsteps = 400
+    specs = [(700, 33, 1.0, 0.2, 1, 0.4), (513, 17, 2.0, 0.2, 1, 0.4),
+             (900, 65, 5.0, 0.1, 1, 0.4)]
+    mems, states, flows = _members(rng, specs, nsteps)
+    flows[1][-1, 257] = 1000.0  # last slice, one site
+    b = Batch(mems)
+    fp = b.pack_state(states)
+    f = torch.from_numpy(fp.copy()).cuda()
+    b.step(f, torch.from_numpy(b.pack_flow(flows)).cuda(), nsteps,
+           graph_steps=50)
+    rc, flags = b.sync(check=False)
+    assert rc == ECFL
+    assert list(flags) == [0, 1, 0]
+    out = b.unpack_state(f.cpu().numpy())
+    assert np.array_equal(out[1], states[1])
+    assert not np.array_equal(out[0], states[0])
+    b.close()
+
+
 def test_batch_256_members_full_size_sampled():
     """256 realizations, nx uniform in [512, 8192], nv in {33, 65, 129},
     St log-uniform in [0.1, 10], own flow each: a few steps on the GPU,
