@@ -297,10 +297,13 @@ def bench_coarse(args, w):
     f = torch.from_numpy(inputs.gaussian_ic(2, n, nvf, dx, dv, ny=n)).cuda()
     for k in range(T_spin):
         fine.step(f, flow_a(k), tau_p, kappa, dt, 1)
+    eps = args.line_eps
+    if not 0 <= eps < 1:
+        sys.exit("--line-eps must be in [0, 1)")
     X, t, wt = CC.collect_samples(fine, coarse, mlp, f, flow_a, steps=T_train,
                                   dt=dt, tau_p=tau_p, kappa=kappa, St=St,
                                   sites_per_step=768, seed=1,
-                                  first_step=T_spin)
+                                  first_step=T_spin, rel_eps=eps)
     n_samples = int(t.numel())
     torch.cuda.synchronize()
     t_train = time.perf_counter()
@@ -313,11 +316,11 @@ def bench_coarse(args, w):
     f0 = torch.from_numpy(inputs.gaussian_ic(2, n, nvf, dx, dv, ny=n)).cuda()
     scale, cal = CC.calibrate_output_scale(fine, cs, mlp, St, f0, flow_c,
                                            steps=T_cal, dt=dt, tau_p=tau_p,
-                                           kappa=kappa)
+                                           kappa=kappa, line_eps=eps)
     log(f"bench: output scale {scale} (calibration variance errors {cal})")
 
     plain, corr = Lattice(cs), Lattice(cs)
-    mlp.attach(corr, St, 1e-3)
+    mlp.attach(corr, St, eps)
     f0 = torch.from_numpy(inputs.gaussian_ic(2, n, nvf, dx, dv, ny=n)).cuda()
     tracks, ff, states = CC.compare(fine, {"plain": plain, "mlp": corr}, f0,
                                     flow_b, steps=T_eval, dt=dt, tau_p=tau_p,
@@ -369,7 +372,7 @@ def bench_coarse(args, w):
                          f"{nvf}^2 velocities (nsub {nsf}) vs stride-4 coarse "
                          f"17^2 (nsub {nsc}) + learned face-flux correction "
                          "(8-64-64-1 GELU, bf16 matrix cores, faces whose "
-                         "stencil holds below 1e-3 of the site mass "
+                         f"stencil holds below {eps:g} of the site mass "
                          f"skipped), St={St}, "
                          f"kappa={kappa}, Vmax={w['vmax']} u_rms, koren; value"
                          " = fine-lattice cell updates per second delivered "
@@ -551,6 +554,11 @@ def main():
                     choices=sorted(WORKLOADS))
     ap.add_argument("--scheme", default="koren", choices=["koren", "upwind"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--line-eps", type=float, default=8e-3,
+                    help="coarse workload: faces whose stencil holds less "
+                         "than this fraction of the site mass get no "
+                         "learned correction (training keeps the same "
+                         "faces)")
     ap.add_argument("--st", type=float, default=None,
                     help="Stokes number instead of the workload's own "
                          "(tau_p = St L / u_rms)")
