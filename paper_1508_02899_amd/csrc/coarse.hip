@@ -731,33 +731,59 @@ __global__ __launch_bounds__(256) void k_mlp_correct17(
         face_feat(ln, NV, k, uy, g, st, ms, sg, anu);
       }
     };
-    if (l < NV) {  // row masses, then the site mass in a fixed order
+    // prefix sums of every velocity line (rows into gx, columns into gy,
+    // which hold the fluxes only later): P[c] = sum of cells < c; the
+    // row masses, then the site mass in a fixed order
+    if (l < NV) {
       float m = 0.f;
-      for (int j = 0; j < NV; ++j) m += tile[l * NV + j][s];
+      gx[w][l][0] = 0.f;
+      for (int j = 0; j < NV; ++j) {
+        m += tile[l * NV + j][s];
+        gx[w][l][j + 1] = m;
+      }
       lm[w][l] = m;
-    }
-    for (int i = l; i < NV * (NV + 1); i += 64) {
-      (&gx[w][0][0])[i] = 0.f;
-      (&gy[w][0][0])[i] = 0.f;
+    } else if (l >= 32 && l < 32 + NV) {
+      const int a = l - 32;
+      float m = 0.f;
+      gy[w][0][a] = 0.f;
+      for (int j = 0; j < NV; ++j) {
+        m += tile[j * NV + a][s];
+        gy[w][j + 1][a] = m;
+      }
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     float M = 0.f;
     for (int j = 0; j < NV; ++j) M += lm[w][j];
     const float thr = g.line_eps * M;
-    // queue of the faces that get a correction
+    // queue of the faces that get a correction: the stencil mass from two
+    // prefix sums (the network's inputs below use the stencil itself)
     int nq = 0;
+    constexpr int H = (NV - 1) / 2;
     for (int f0 = 0; f0 < NFACE; f0 += 64) {
       const int fid = f0 + l;
       bool use = false;
       if (fid < NFACE) {
-        float st[5], ms, sg, anu;
-        feat(fid, st, &ms, &sg, &anu);
+        int axis, a, k;
+        face_of(fid, &axis, &a, &k);
+        const float vface = ((float)k - 0.5f - (float)H) * g.dv;
+        const float nu = g.nu_scale * ((axis == 0 ? ux : uy) - vface);
+        const int lo = nu >= 0.f ? k - 3 : k - 2;  // stencil cells lo..lo+4
+        const int c0 = lo < 0 ? 0 : lo;
+        const int c1 = lo + 5 > NV ? NV : lo + 5;
+        const float ms = axis == 0 ? gx[w][a][c1] - gx[w][a][c0]
+                                   : gy[w][c1][a] - gy[w][c0][a];
         use = ms > kMinStencilMass && ms >= thr;
       }
       const uint64_t b = __ballot(use);
       if (use) queue[w][nq + __popcll(b & below)] = (uint16_t)fid;
       nq += __popcll(b);
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    for (int i = l; i < NV * (NV + 1); i += 64) {
+      (&gx[w][0][0])[i] = 0.f;
+      (&gy[w][0][0])[i] = 0.f;
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
