@@ -703,23 +703,47 @@ __global__ __launch_bounds__(256) void k_mlp_correct17(
   __shared__ float gy[4][NV + 1][NV];  // y-face fluxes [face 0..NV][col]
   __shared__ float lm[4][NV];          // row masses
   __shared__ uint16_t queue[4][NFACE];
+  __shared__ float us[2][kTS];  // flow at the tile's sites
   if (*flag != 0) return;
-  MlpRegs R;
-  load_mlp(R, P, wq);
   const int tid = (int)threadIdx.x, l = tid & 63, w = tid >> 6;
   const int64_t S = (int64_t)g.nx * g.ny;
   const int64_t s0 = (int64_t)blockIdx.x * kTS;
   const int nts = (int)((S - s0) < kTS ? (S - s0) : kTS);
-  for (int i = tid; i < N2 * kTS; i += 256) {
-    const int J = i / kTS, s = i - J * kTS;
-    tile[J][s] = s < nts ? f[(size_t)J * S + s0 + s] : 0.f;
+  // every load of a thread is issued before the first LDS write, so the
+  // tile costs one memory latency, not one per element.  Thread tid moves
+  // site ls of planes lj, lj + JP, ...; loads past the tile's end read
+  // plane 0 of a valid site instead and are dropped
+  constexpr int JP = 256 / kTS, NL = (N2 + JP - 1) / JP;
+  static_assert(256 % kTS == 0, "whole planes per pass");
+  const int ls = tid % kTS, lj = tid / kTS;
+  const bool lsv = ls < nts;
+  const float* const fsite = f + s0 + (lsv ? ls : 0);
+  const size_t pstride = (size_t)JP * (size_t)S;
+  {
+    float v[NL];
+    const float* p = fsite + (size_t)lj * (size_t)S;
+#pragma unroll
+    for (int it = 0; it < NL; ++it) {
+      v[it] = *(lj + JP * it < N2 ? p : fsite);
+      p += pstride;
+    }
+    if (tid < 2 * kTS) {
+      const int c = tid / kTS, s = tid - c * kTS;
+      us[c][s] = s < nts ? u[c * S + s0 + s] : 0.f;
+    }
+#pragma unroll
+    for (int it = 0; it < NL; ++it) {
+      const int J = lj + JP * it;
+      if (J < N2) tile[J][ls] = lsv ? v[it] : 0.f;
+    }
   }
+  MlpRegs R;
+  load_mlp(R, P, wq);
   __syncthreads();
   const int col = l & 15, ks = l >> 4;
   const uint64_t below = (l == 0) ? 0ull : (~0ull >> (64 - l));
   for (int s = w; s < nts; s += 4) {
-    const int64_t site = s0 + s;
-    const float ux = u[site], uy = u[S + site];
+    const float ux = us[0][s], uy = us[1][s];
     auto feat = [&](int fid, float* st, float* ms, float* sg, float* anu) {
       int axis, a, k;
       face_of(fid, &axis, &a, &k);
@@ -827,9 +851,19 @@ __global__ __launch_bounds__(256) void k_mlp_correct17(
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   }
   __syncthreads();
-  for (int i = tid; i < N2 * kTS; i += 256) {
-    const int J = i / kTS, s = i - J * kTS;
-    if (s < nts) f[(size_t)J * S + s0 + s] = tile[J][s];
+  {
+    float v[NL];
+#pragma unroll
+    for (int it = 0; it < NL; ++it) {
+      const int J = lj + JP * it;
+      v[it] = J < N2 ? tile[J][ls] : 0.f;
+    }
+    float* p = f + s0 + ls + (size_t)lj * (size_t)S;
+#pragma unroll
+    for (int it = 0; it < NL; ++it) {
+      if (lsv && lj + JP * it < N2) *p = v[it];
+      p += pstride;
+    }
   }
 }
 
