@@ -701,7 +701,6 @@ __global__ __launch_bounds__(256) void k_mlp_correct17(
   __shared__ float tile[N2][kTS + 1];
   __shared__ float gx[4][NV][NV + 1];  // x-face fluxes [row][face 0..NV]
   __shared__ float gy[4][NV + 1][NV];  // y-face fluxes [face 0..NV][col]
-  __shared__ float lm[4][NV];          // row masses
   __shared__ uint16_t queue[4][NFACE];
   __shared__ float us[2][kTS];  // flow at the tile's sites
   if (*flag != 0) return;
@@ -744,67 +743,51 @@ __global__ __launch_bounds__(256) void k_mlp_correct17(
   const uint64_t below = (l == 0) ? 0ull : (~0ull >> (64 - l));
   for (int s = w; s < nts; s += 4) {
     const float ux = us[0][s], uy = us[1][s];
+    // a face's line as a base and a stride into the tile, so that x- and
+    // y-faces in one pass of 16 take the same instructions
     auto feat = [&](int fid, float* st, float* ms, float* sg, float* anu) {
       int axis, a, k;
       face_of(fid, &axis, &a, &k);
-      if (axis == 0) {
-        auto ln = [&](int c) { return tile[a * NV + c][s]; };
-        face_feat(ln, NV, k, ux, g, st, ms, sg, anu);
-      } else {
-        auto ln = [&](int c) { return tile[c * NV + a][s]; };
-        face_feat(ln, NV, k, uy, g, st, ms, sg, anu);
-      }
+      const int base = axis == 0 ? a * NV : a, stride = axis == 0 ? 1 : NV;
+      auto ln = [&](int c) { return tile[base + c * stride][s]; };
+      face_feat(ln, NV, k, axis == 0 ? ux : uy, g, st, ms, sg, anu);
     };
-    // prefix sums of every velocity line (rows into gx, columns into gy,
-    // which hold the fluxes only later): P[c] = sum of cells < c; the
-    // row masses, then the site mass in a fixed order
-    if (l < NV) {
-      float m = 0.f;
-      gx[w][l][0] = 0.f;
-      for (int j = 0; j < NV; ++j) {
-        m += tile[l * NV + j][s];
-        gx[w][l][j + 1] = m;
-      }
-      lm[w][l] = m;
-    } else if (l >= 32 && l < 32 + NV) {
-      const int a = l - 32;
-      float m = 0.f;
-      gy[w][0][a] = 0.f;
-      for (int j = 0; j < NV; ++j) {
-        m += tile[j * NV + a][s];
-        gy[w][j + 1][a] = m;
-      }
-    }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    // the faces that get a correction: lanes 0..NV-1 take the rows (x-faces),
+    // lanes 32..32+NV-1 the columns (y-faces) of the site; each keeps the
+    // prefix sums of its line in registers (Pf[c] = sum of the cells < c)
+    // and takes a face's stencil mass from two of them; the site mass sums
+    // the row masses in row order
+    const bool rl = l < NV, cl = l >= 32 && l < 32 + NV;
+    const int la = rl ? l : (cl ? l - 32 : 0);
+    float Pf[NV + 1];
+    Pf[0] = 0.f;
+#pragma unroll
+    for (int j = 0; j < NV; ++j)
+      Pf[j + 1] = Pf[j] + tile[rl ? la * NV + j : j * NV + la][s];
     float M = 0.f;
-    for (int j = 0; j < NV; ++j) M += lm[w][j];
+#pragma unroll
+    for (int j = 0; j < NV; ++j)
+      M += __int_as_float(
+          __builtin_amdgcn_readlane(__float_as_int(Pf[NV]), j));
     const float thr = g.line_eps * M;
-    // queue of the faces that get a correction: the stencil mass from two
-    // prefix sums (the network's inputs below use the stencil itself)
-    int nq = 0;
+    const float uax = rl ? ux : uy;
+    const int fbase = (cl ? NV * (NV - 1) : 0) + la * (NV - 1) - 1;
     constexpr int H = (NV - 1) / 2;
-    for (int f0 = 0; f0 < NFACE; f0 += 64) {
-      const int fid = f0 + l;
-      bool use = false;
-      if (fid < NFACE) {
-        int axis, a, k;
-        face_of(fid, &axis, &a, &k);
-        const float vface = ((float)k - 0.5f - (float)H) * g.dv;
-        const float nu = g.nu_scale * ((axis == 0 ? ux : uy) - vface);
-        const int lo = nu >= 0.f ? k - 3 : k - 2;  // stencil cells lo..lo+4
-        const int c0 = lo < 0 ? 0 : lo;
-        const int c1 = lo + 5 > NV ? NV : lo + 5;
-        const float ms = axis == 0 ? gx[w][a][c1] - gx[w][a][c0]
-                                   : gy[w][c1][a] - gy[w][c0][a];
-        use = ms > kMinStencilMass && ms >= thr;
-      }
+    int nq = 0;
+#pragma unroll
+    for (int k = 1; k < NV; ++k) {
+      const float vface = ((float)k - 0.5f - (float)H) * g.dv;
+      const float nu = g.nu_scale * (uax - vface);
+      // stencil cells lo..lo+4 (lo = k-3 upwind from below, else k-2),
+      // clipped to the line
+      const float ms = nu >= 0.f
+                           ? Pf[k + 2 < NV ? k + 2 : NV] - Pf[k - 3 > 0 ? k - 3 : 0]
+                           : Pf[k + 3 < NV ? k + 3 : NV] - Pf[k - 2 > 0 ? k - 2 : 0];
+      const bool use = (rl || cl) && ms > kMinStencilMass && ms >= thr;
       const uint64_t b = __ballot(use);
-      if (use) queue[w][nq + __popcll(b & below)] = (uint16_t)fid;
+      if (use) queue[w][nq + __popcll(b & below)] = (uint16_t)(fbase + k);
       nq += __popcll(b);
     }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     for (int i = l; i < NV * (NV + 1); i += 64) {
       (&gx[w][0][0])[i] = 0.f;
       (&gy[w][0][0])[i] = 0.f;
@@ -830,22 +813,23 @@ __global__ __launch_bounds__(256) void k_mlp_correct17(
         int axis, a, k;
         face_of(fid, &axis, &a, &k);
         float G = sg * ms * y;
-        const float donor = axis == 0 ? tile[a * NV + (G > 0.f ? k - 1 : k)][s]
-                                      : tile[(G > 0.f ? k - 1 : k) * NV + a][s];
+        const int base = axis == 0 ? a * NV : a, stride = axis == 0 ? 1 : NV;
+        const float donor = tile[base + (G > 0.f ? k - 1 : k) * stride][s];
         const float cap = 0.25f * donor;
         G = G > cap ? cap : (G < -cap ? -cap : G);
-        if (axis == 0)
-          gx[w][a][k] = G;
-        else
-          gy[w][k][a] = G;
+        *(axis == 0 ? &gx[w][a][k] : &gy[w][k][a]) = G;
       }
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    for (int J = l; J < N2; J += 64) {
-      const int jy = J / NV, jx = J - jy * NV;
-      tile[J][s] -= (gx[w][jy][jx + 1] - gx[w][jy][jx]) +
-                    (gy[w][jy + 1][jx] - gy[w][jy][jx]);
+#pragma unroll
+    for (int it = 0; it < (N2 + 63) / 64; ++it) {
+      const int J = l + 64 * it;
+      if (J < N2) {
+        const int jy = J / NV, jx = J - jy * NV;
+        tile[J][s] -= (gx[w][jy][jx + 1] - gx[w][jy][jx]) +
+                      (gy[w][jy + 1][jx] - gy[w][jy][jx]);
+      }
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
