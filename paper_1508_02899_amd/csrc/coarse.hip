@@ -147,6 +147,33 @@ __device__ __forceinline__ float mlp_forward(const MlpRegs& R, bf16x4 x) {
   return y[0];
 }
 
+// The same network with the layer biases read from LDS (b1s, b2s: the 64
+// biases of each hidden layer, 16-byte aligned): a kernel that keeps the
+// weights in registers for its whole run frees the 32 bias registers.
+__device__ __forceinline__ float mlp_forward_lds(const MlpRegs& R,
+                                                 const float* b1s,
+                                                 const float* b2s, bf16x4 x) {
+  const int ks = ((int)threadIdx.x & 63) >> 4;
+  bf16x4 h1[4], h2[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const f32x4 b = *(const f32x4*)(b1s + 16 * u + 4 * ks);
+    const f32x4 d = mfma16(R.a1[u], x, b);
+    h1[u] = pack4(gelu(d[0]), gelu(d[1]), gelu(d[2]), gelu(d[3]));
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    f32x4 d = *(const f32x4*)(b2s + 16 * u + 4 * ks);
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) d = mfma16(R.a2[u][kk], h1[kk], d);
+    h2[u] = pack4(gelu(d[0]), gelu(d[1]), gelu(d[2]), gelu(d[3]));
+  }
+  f32x4 y = {R.b3, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) y = mfma16(R.a3[kk], h2[kk], y);
+  return y[0];
+}
+
 // -------------------------------------------------------------- restriction
 // Coarse cell J spans fine centres 4J-2..4J+2: fine cells 4J-1..4J+1 count
 // fully, 4J+-2 half (tensor product in 2D); densities scale by 1/4 per axis.
@@ -692,7 +719,7 @@ __device__ __forceinline__ void face_of(int fid, int* axis, int* a, int* k) {
   *k = r - *a * (kNVC - 1) + 1;
 }
 
-__global__ __launch_bounds__(256) void k_mlp_correct17(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_mlp_correct17(
     CoarseGeom g, const float* __restrict__ P, const uint16_t* __restrict__ wq,
     float* __restrict__ f, const float* __restrict__ u,
     const int* __restrict__ flag) {
@@ -703,6 +730,7 @@ __global__ __launch_bounds__(256) void k_mlp_correct17(
   __shared__ float gy[4][NV + 1][NV];  // y-face fluxes [face 0..NV][col]
   __shared__ uint16_t queue[4][NFACE];
   __shared__ float us[2][kTS];  // flow at the tile's sites
+  __shared__ __align__(16) float bsh[2][kNH];  // hidden-layer biases
   if (*flag != 0) return;
   const int tid = (int)threadIdx.x, l = tid & 63, w = tid >> 6;
   const int64_t S = (int64_t)g.nx * g.ny;
@@ -736,6 +764,8 @@ __global__ __launch_bounds__(256) void k_mlp_correct17(
       if (J < N2) tile[J][ls] = lsv ? v[it] : 0.f;
     }
   }
+  if (tid < 2 * kNH)
+    bsh[tid / kNH][tid % kNH] = P[(tid < kNH ? kOffB1 : kOffB2) + tid % kNH];
   MlpRegs R;
   load_mlp(R, P, wq);
   __syncthreads();
@@ -761,9 +791,12 @@ __global__ __launch_bounds__(256) void k_mlp_correct17(
     const int la = rl ? l : (cl ? l - 32 : 0);
     float Pf[NV + 1];
     Pf[0] = 0.f;
+    {
+      const float* lp = &tile[rl ? la * NV : la][s];
+      const int lstep = (rl ? 1 : NV) * (kTS + 1);
 #pragma unroll
-    for (int j = 0; j < NV; ++j)
-      Pf[j + 1] = Pf[j] + tile[rl ? la * NV + j : j * NV + la][s];
+      for (int j = 0; j < NV; ++j) Pf[j + 1] = Pf[j] + lp[j * lstep];
+    }
     float M = 0.f;
 #pragma unroll
     for (int j = 0; j < NV; ++j)
@@ -808,7 +841,7 @@ __global__ __launch_bounds__(256) void k_mlp_correct17(
         x = pack4(st[4] * inv, anu, g.log_st, 0.f);
       else
         x = pack4(0.f, 0.f, 0.f, 0.f);
-      const float y = mlp_forward(R, x);
+      const float y = mlp_forward_lds(R, bsh[0], bsh[1], x);
       if (l < 16 && live) {
         int axis, a, k;
         face_of(fid, &axis, &a, &k);
