@@ -152,16 +152,18 @@ def test_adam_step_matches_oracle():
     m.close()
 
 
-def _coarse_case(rng, n=6):
-    """A coarse 17^2 state at n x n sites and a 'true' state of equal mass."""
+def _coarse_case(rng, n=6, ny=None):
+    """A coarse 17^2 state at n x ny sites (ny = n by default) and a 'true'
+    state of equal mass."""
     nv = 17
-    f_pred = (rng.random((nv * nv, n, n)) ** 3).astype(np.float32)
+    ny = n if ny is None else ny
+    f_pred = (rng.random((nv * nv, ny, n)) ** 3).astype(np.float32)
     f_true = (f_pred * (1 + 0.1 * rng.standard_normal(f_pred.shape))).astype(np.float32)
     f_true = np.abs(f_true)
     s_p = f_pred.sum(axis=0, dtype=np.float64)
     s_t = f_true.sum(axis=0, dtype=np.float64)
     f_true = (f_true * (s_p / s_t)[None]).astype(np.float32)
-    u = (0.8 * np.tanh(rng.standard_normal((1, 2, n, n)))).astype(np.float32)
+    u = (0.8 * np.tanh(rng.standard_normal((1, 2, ny, n)))).astype(np.float32)
     return f_pred, f_true, u
 
 
@@ -262,18 +264,21 @@ def test_natural_flux_samples_match_oracle(scheme, nsf, nsc):
     coarse.close()
 
 
-def test_correction_pass_matches_oracle_and_conserves_mass():
+@pytest.mark.parametrize("n,ny", [(8, 8), (12, 7)])
+def test_correction_pass_matches_oracle_and_conserves_mass(n, ny):
     """A coarse 2D step with the network attached vs plain step + the
-    oracle's correction of every site."""
+    oracle's correction of every site.  12 x 7 = 84 sites: the correction
+    kernel's last tile of 32 sites is partly empty."""
     import torch
     from oracle import coarse as C
     from paper_1508_02899_amd import Lattice, LatticeSpec, Mlp
     rng = np.random.default_rng(38)
-    n, nv = 8, 17
-    f0, _, u = _coarse_case(rng, n)
+    nv = 17
+    say(f"  correction pass, {n} x {ny} sites")
+    f0, _, u = _coarse_case(rng, n, ny)
     dx = 2 * math.pi / n
     dt, tau_p, St, kappa, eps = 0.05, 40.0, 1.5, 0.0, 1e-3
-    spec = LatticeSpec(dim=2, nx=n, ny=n, nv=nv, dx=dx, vstride=4)
+    spec = LatticeSpec(dim=2, nx=n, ny=ny, nv=nv, dx=dx, vstride=4)
     P = _params(rng, 0.3)
     P["b3"] = np.array(0.05)
     plain = Lattice(spec)
@@ -292,7 +297,7 @@ def test_correction_pass_matches_oracle_and_conserves_mass():
     dv = 4 * dx / dt
     Pq = _unpack(_pack(P))
     want = np.empty_like(mid)
-    for y in range(n):
+    for y in range(ny):
         for x in range(n):
             c = mid[:, y, x]
             Xo, ms, sg = C.face_features(c, nv, float(u[0, 0, y, x]),
