@@ -770,7 +770,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   load_mlp(R, P, wq);
   __syncthreads();
   const int col = l & 15, ks = l >> 4;
-  const uint64_t below = (l == 0) ? 0ull : (~0ull >> (64 - l));
   for (int s = w; s < nts; s += 4) {
     const float ux = us[0][s], uy = us[1][s];
     // a face's line as a base and a stride into the tile, so that x- and
@@ -818,7 +817,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                            : Pf[k + 3 < NV ? k + 3 : NV] - Pf[k - 2 > 0 ? k - 2 : 0];
       const bool use = (rl || cl) && ms > kMinStencilMass && ms >= thr;
       const uint64_t b = __ballot(use);
-      if (use) queue[w][nq + __popcll(b & below)] = (uint16_t)(fbase + k);
+      // lanes below this one with a face (v_mbcnt)
+      const int before = (int)__builtin_amdgcn_mbcnt_hi(
+          (uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+      if (use) queue[w][nq + before] = (uint16_t)(fbase + k);
       nq += __popcll(b);
     }
     for (int i = l; i < NV * (NV + 1); i += 64) {
