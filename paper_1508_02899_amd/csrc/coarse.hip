@@ -779,11 +779,14 @@ void k_mlp_correct17(
     const float ux = us[0][s], uy = us[1][s];
     // a face's line as a base and a stride into the tile, so that x- and
     // y-faces in one pass of 16 take the same instructions
+    // (24-bit index products: full-rate multiplies)
+    const float* const tcol = &tile[0][s];
     auto feat = [&](int fid, float* st, float* ms, float* sg, float* anu) {
       int axis, a, k;
       face_of(fid, &axis, &a, &k);
-      const int base = axis == 0 ? a * NV : a, stride = axis == 0 ? 1 : NV;
-      auto ln = [&](int c) { return tile[base + c * stride][s]; };
+      const int boff = __umul24(axis == 0 ? a * NV : a, kTS + 1);
+      const int soff = axis == 0 ? kTS + 1 : NV * (kTS + 1);
+      auto ln = [&](int c) { return tcol[boff + __umul24(c, soff)]; };
       face_feat(ln, NV, k, axis == 0 ? ux : uy, g, st, ms, sg, anu);
     };
     // the faces that get a correction: lanes 0..NV-1 take the rows (x-faces),
@@ -840,7 +843,8 @@ void k_mlp_correct17(
       const int fid = live ? (int)queue[w][e] : 0;
       float st[5], ms, sg, anu;
       feat(fid, st, &ms, &sg, &anu);
-      const float inv = ms > 0.f ? 1.0f / ms : 0.f;
+      // 1/m_s to 1 ulp (the features are rounded to bf16 next)
+      const float inv = ms > 0.f ? __builtin_amdgcn_rcpf(ms) : 0.f;
       bf16x4 x;
       if (ks == 0 && live)
         x = pack4(st[0] * inv, st[1] * inv, st[2] * inv, st[3] * inv);
@@ -853,8 +857,9 @@ void k_mlp_correct17(
         int axis, a, k;
         face_of(fid, &axis, &a, &k);
         float G = sg * ms * y;
-        const int base = axis == 0 ? a * NV : a, stride = axis == 0 ? 1 : NV;
-        const float donor = tile[base + (G > 0.f ? k - 1 : k) * stride][s];
+        const int boff = __umul24(axis == 0 ? a * NV : a, kTS + 1);
+        const int soff = axis == 0 ? kTS + 1 : NV * (kTS + 1);
+        const float donor = tcol[boff + __umul24(G > 0.f ? k - 1 : k, soff)];
         const float cap = 0.25f * donor;
         G = G > cap ? cap : (G < -cap ? -cap : G);
         *(axis == 0 ? &gx[w][a][k] : &gy[w][k][a]) = G;
