@@ -72,7 +72,7 @@ __global__ __launch_bounds__(parts_threads<NV>()) void k_batch1d_parts(
     int local_step) {
   constexpr int P = BatchShape<NV>::P, WGW = BatchShape<NV>::WGW;
   using PT = Parts1DTile<float, NV, P, WGW>;
-  __shared__ float tile[NV * PT::STRIDE];
+  __shared__ float tile[PT::SIZE];
   const int step = *step_base + local_step;
   // next work item of this workgroup at or after w, skipping frozen
   // members (uniform over the workgroup)

@@ -35,25 +35,42 @@ struct Parts1D {
   static constexpr int DW = sizeof(T) / 4;    // dwords per element
   static_assert((NV - 1) % P == 0, "parts must tile the velocity axis");
   static_assert(W >= 3, "the halo exchange needs 3 cells per part");
-  // LDS padding: the P parts of a wavefront read rows p(W-1) + i of S
-  // consecutive columns; pick the smallest padding that puts the 64 lanes
-  // of one read in distinct banks.
+  // LDS layout: plane j at j STRIDE + (j / (W-1)) SKEW elements.  The P
+  // parts of a wavefront read rows p(W-1) + i of S consecutive columns; the
+  // padding of a plane is the smallest that puts the 64 lanes of one read in
+  // distinct banks.  Where no padding can (parts W-1 = 16 planes apart: a
+  // plane offset times 16 reaches only 4 of the 8 bank groups that 8 parts
+  // need), a skew per block of W-1 planes separates the parts instead.
+  static constexpr bool banks_ok(int pd, int sk) {
+    bool used[64] = {};
+    for (int p = 0; p < P; ++p)
+      for (int sl = 0; sl < S; ++sl)
+        for (int d = 0; d < DW; ++d) {
+          const int bank = ((p * (W - 1) * (G + pd) + p * sk + sl) * DW + d) % 64;
+          if (used[bank]) return false;
+          used[bank] = true;
+        }
+    return true;
+  }
   static constexpr int pad() {
-    for (int pd = 0; pd < 64; ++pd) {
-      bool used[64] = {};
-      bool ok = true;
-      for (int p = 0; p < P && ok; ++p)
-        for (int sl = 0; sl < S && ok; ++sl)
-          for (int d = 0; d < DW && ok; ++d) {
-            const int bank = ((p * (W - 1) * (G + pd) + sl) * DW + d) % 64;
-            if (used[bank]) ok = false;
-            used[bank] = true;
-          }
-      if (ok || P * S * DW > 64) return pd;
-    }
+    if (P * S * DW > 64) return 0;  // two or more elements per bank anyway
+    for (int pd = 0; pd < 64; ++pd)
+      if (banks_ok(pd, 0)) return pd;
+    return 0;
+  }
+  static constexpr int skew() {
+    if (P * S * DW > 64 || banks_ok(pad(), 0)) return 0;
+    for (int sk = 1; sk < 64; ++sk)
+      if (banks_ok(0, sk)) return sk;
     return 0;
   }
   static constexpr int STRIDE = G + pad();  // elements per LDS plane
+  static constexpr int SKEW = skew();       // elements per block of W-1 planes
+  static constexpr int SIZE = NV * STRIDE + P * SKEW;  // tile elements
+  // offset of plane j in the tile
+  __device__ __forceinline__ static constexpr int row(int j) {
+    return j * STRIDE + (SKEW ? (j / (W - 1)) * SKEW : 0);
+  }
 };
 
 // Parts and wavefronts per workgroup for each compiled velocity lattice
@@ -71,7 +88,7 @@ template <> struct PartsShape<double, 65> { static constexpr int P = 8, WGW = 4;
 
 // The phases of the update of the tile of sites x0 .. x0+G-1 of one
 // lattice [NV][nx] by one workgroup (every thread of the workgroup calls
-// each phase; the tile is NV * STRIDE elements of LDS).  The loads and
+// each phase; the tile is SIZE elements of LDS).  The loads and
 // stores move whole planes: thread (fj0, fs) = (tid / G, tid % G) moves
 // planes fj0 + P k, k < K, of site fs (the workgroup has 64 WGW = P G
 // threads).  No implicit multiply-add contraction anywhere: the fused
@@ -81,7 +98,7 @@ template <typename T, int NV, int P, int WGW>
 struct Parts1DTile {
   using C = Parts1D<T, NV, P, WGW>;
   static constexpr int W = C::W, S = C::S, G = C::G, H = C::H, K = C::K;
-  static constexpr int STRIDE = C::STRIDE;
+  static constexpr int STRIDE = C::STRIDE, SKEW = C::SKEW, SIZE = C::SIZE;
 
   // 1a. pull streaming: plane j of site x comes from (x - s(j-h)) mod nx;
   // jump = (P s) mod nx, step_mod = s mod nx, init_off = (s h) mod nx.
@@ -122,7 +139,7 @@ struct Parts1DTile {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int j = fj0 + P * k;
-      if (k < K - 1 || j < NV) tile[j * STRIDE + fs] = r[k];
+      if (k < K - 1 || j < NV) tile[C::row(j) + fs] = r[k];
     }
   }
 
@@ -154,7 +171,8 @@ struct Parts1DTile {
     const bool first = p == 0, last = p == P - 1;
     const int lane_l = lane - S, lane_r = lane + S;
     const int j0 = p * (W - 1);
-    T* col = tile + j0 * STRIDE + lane_site();
+    T* col = tile + j0 * STRIDE + p * SKEW + lane_site();  // = row(j0 + i)
+    // for i < W-1; the part's last cell lies in the next block
 
     T nup[W + 2], num[W + 2];  // split coefficients of cells -1 .. W
 #pragma unroll
@@ -165,7 +183,8 @@ struct Parts1DTile {
     }
     T c[W];
 #pragma unroll
-    for (int i = 0; i < W; ++i) c[i] = col[i * STRIDE];
+    for (int i = 0; i < W - 1; ++i) c[i] = col[i * STRIDE];
+    c[W - 1] = col[(W - 1) * STRIDE + SKEW];
 
 #pragma unroll 1
     for (int sub = 0; sub < nsub; ++sub) {
@@ -227,7 +246,7 @@ struct Parts1DTile {
     }
 #pragma unroll
     for (int i = 0; i < W - 1; ++i) col[i * STRIDE] = c[i];
-    if (last) col[(W - 1) * STRIDE] = c[W - 1];
+    if (last) col[(W - 1) * STRIDE + SKEW] = c[W - 1];
   }
 
   // 3. plane-by-plane stores of the finished tile
@@ -242,7 +261,7 @@ struct Parts1DTile {
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         const int j = fj0 + P * k;
-        if (k < K - 1 || j < NV) fout[(size_t)j * nx + ox] = tile[j * STRIDE + fs];
+        if (k < K - 1 || j < NV) fout[(size_t)j * nx + ox] = tile[C::row(j) + fs];
       }
     }
   }

@@ -17,7 +17,7 @@ __global__ __launch_bounds__(64 * WGW) void k_step1d_parts(
     const int* __restrict__ flag, int nx, int step_mod, int init_off,
     int jump, int nsub, T alpha_scale, T beta, T D, int nblocks) {
   using C = Parts1D<T, NV, P, WGW>;
-  __shared__ T tile[NV * C::STRIDE];
+  __shared__ T tile[C::SIZE];
   if (*flag != 0) return;  // uniform over the grid
   const int xg = xcd_remap(blockIdx.x, nblocks);
   parts1d_tile<T, NV, P, WGW, KOREN>(fin, fout, u, tile, nx, xg * C::G,
