@@ -675,15 +675,15 @@ def main():
     if W:
         run_steps(0, W)
         lat.sync()
-    # Launch durations: HIP events around every step launch on the
-    # library's stream, inside the timed region, for the 2D lattices
-    # (launches of hundreds of us).  A 1D step lasts a few us and an event
-    # pair per launch would add its own latency, so there the K launches of
-    # a second pass of the same steps right after the timed region are
-    # timed back to back by one event pair on the same stream.
-    inline_events = dim == 2
+    # Launch durations: the K launches of a second pass of the same steps
+    # right after the timed region, timed back to back by one event pair
+    # on the library's stream (torch's current one).  Events around every
+    # launch inside the timed region cost time themselves: measured on
+    # configuration 3, 464 us per launch that way against 457 us back to
+    # back, and a 1.5 % lower whole-run rate; a 1D step lasts a few us and
+    # an event pair per launch would add its own latency.
     torch.cuda.synchronize()
-    lat.profile(inline_events)
+    lat.profile(False)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
@@ -694,19 +694,14 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ev_ms = ev0.elapsed_time(ev1)
-    if inline_events:
-        kern_ms, launches = lat.profile_read()
-        lat.profile(False)
-    else:
-        lat.profile(False)
-        ev2 = torch.cuda.Event(enable_timing=True)
-        ev3 = torch.cuda.Event(enable_timing=True)
-        ev2.record()
-        run_steps(W, K)
-        ev3.record()
-        torch.cuda.synchronize()
-        lat.sync()
-        kern_ms, launches = ev2.elapsed_time(ev3), K
+    ev2 = torch.cuda.Event(enable_timing=True)
+    ev3 = torch.cuda.Event(enable_timing=True)
+    ev2.record()
+    run_steps(W, K)
+    ev3.record()
+    torch.cuda.synchronize()
+    lat.sync()
+    kern_ms, launches = ev2.elapsed_time(ev3), K
     if args.copy_calibration:
         g = torch.empty_like(f)
         lat.copy_state(g, f)
@@ -770,9 +765,7 @@ def main():
             "traffic": traffic,
             "kernel": step_kernel(dim, n, nv, w["dtype"]),
             "avg_launch_us": round(avg_launch_s * 1e6, 3),
-            "launch_timing": ("HIP events around each launch in the timed "
-                              "region" if inline_events else
-                              "one HIP event pair around the K back-to-back "
+            "launch_timing": ("one HIP event pair around the K back-to-back "
                               "launches of a second pass of the same steps "
                               "after the timed region"),
             "algorithmic_bytes_per_launch": algo_bytes,
