@@ -701,7 +701,9 @@ def main():
     ev3.record()
     torch.cuda.synchronize()
     lat.sync()
-    kern_ms, launches = ev2.elapsed_time(ev3), K
+    # a 2D step is nsub passes (the later ones collision only), each
+    # reading and writing the whole state; a 1D step is one launch
+    kern_ms, launches = ev2.elapsed_time(ev3), K * (nsub if dim == 2 else 1)
     if args.copy_calibration:
         g = torch.empty_like(f)
         lat.copy_state(g, f)
@@ -765,9 +767,11 @@ def main():
             "traffic": traffic,
             "kernel": step_kernel(dim, n, nv, w["dtype"]),
             "avg_launch_us": round(avg_launch_s * 1e6, 3),
-            "launch_timing": ("one HIP event pair around the K back-to-back "
-                              "launches of a second pass of the same steps "
-                              "after the timed region"),
+            "launch_timing": ("one HIP event pair around the back-to-back "
+                              "launches of a second pass of the same K steps "
+                              "after the timed region"
+                              + (" (the pass includes the flow synthesis "
+                                 "kernels)" if device_flow else "")),
             "algorithmic_bytes_per_launch": algo_bytes,
         },
     }
