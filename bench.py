@@ -598,7 +598,7 @@ def main():
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the lattice update runs on a single "
-              "MI355X in this build (multi-GPU sharding is not built); use "
+              "MI355X (sharding over several GPUs is not implemented); use "
               "--gpus 1", file=sys.stderr)
         sys.exit(2)
 

@@ -16,7 +16,7 @@ def pytest_configure(config):
 
 def pytest_collection_modifyitems(config, items):
     # GPU tests are skipped (not failed) when no GPU is visible, so that the
-    # CPU suite can run everything else; on a GPU machine they run normally.
+    # CPU suite can run everything else; with a GPU they run normally.
     try:
         import torch
         have_gpu = torch.cuda.is_available()
