@@ -270,7 +270,7 @@ def bench_coarse(args, w):
     K, W = args.steps, args.warmup
     L, dx, dv, dt, tau_p = geometry(w)
     n, nvf, St, kappa = w["n"], w["nv"], w["St"], w["kappa"]
-    T_spin, T_train, T_eval = 60, 100, 200
+    T_spin, T_train, T_eval = 60, 200, 200
 
     def flow(seed, nsl):
         u = torch.from_numpy(inputs.flow2d_streamfunction(
@@ -303,13 +303,13 @@ def bench_coarse(args, w):
         sys.exit("--line-eps must be in [0, 1)")
     X, t, wt = CC.collect_samples(fine, coarse, mlp, f, flow_a, steps=T_train,
                                   dt=dt, tau_p=tau_p, kappa=kappa, St=St,
-                                  sites_per_step=768, seed=1,
+                                  sites_per_step=2048, seed=1,
                                   first_step=T_spin, rel_eps=eps)
     n_samples = int(t.numel())
     torch.cuda.synchronize()
     t_train = time.perf_counter()
     for lr in (3e-3, 1e-3, 3e-4):
-        loss = mlp.train(X, t, wt, batch=8192, steps=9000, lr=lr)
+        loss = mlp.train(X, t, wt, batch=8192, steps=27000, lr=lr)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t_train
     del X, t, wt
@@ -389,9 +389,9 @@ def bench_coarse(args, w):
             "timing": ("one lattice_step call of K steps per lattice, a new "
                        "flow slice per step"),
             "speedup_vs_fine": round(ms_fine / ms_mlp, 3),
-            "training": {"samples": n_samples, "adam_steps": 27000,
+            "training": {"samples": n_samples, "adam_steps": 81000,
                          "batch": 8192, "seconds": round(t_train, 3),
-                         "samples_per_s": round(27000 * 8192 / t_train)},
+                         "samples_per_s": round(81000 * 8192 / t_train)},
             "output_scale": scale,
             "calibration_variance_errors": {str(k): round(v, 5)
                                             for k, v in cal.items()},
@@ -562,7 +562,7 @@ def main():
                     choices=sorted(WORKLOADS))
     ap.add_argument("--scheme", default="koren", choices=["koren", "upwind"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--line-eps", type=float, default=8e-3,
+    ap.add_argument("--line-eps", type=float, default=1.4e-2,
                     help="coarse workload: faces whose stencil holds less "
                          "than this fraction of the site mass get no "
                          "learned correction (training keeps the same "
