@@ -81,12 +81,16 @@ __device__ __forceinline__ T row_load(const T* row, uint32_t cell_off,
   asm("" : "+s"(b));
   return *(const LAT_GLOBAL T*)((const LAT_GLOBAL char*)b + lane_off);
 }
+// The stores are non-temporal: a finished row is not read again by the
+// pass that writes it (measured on the 2D pass at 512^2 x 33^2: 1.9 %
+// shorter; non-temporal loads are 18 % longer, since neighbouring tiles
+// read overlapping source lines through the cache).
 template <typename T>
 __device__ __forceinline__ void row_store(T* row, uint32_t cell_off,
                                           uint32_t lane_off, T v) {
   char* b = (char*)row + cell_off;
   asm("" : "+s"(b));
-  *(LAT_GLOBAL T*)((LAT_GLOBAL char*)b + lane_off) = v;
+  __builtin_nontemporal_store(v, (LAT_GLOBAL T*)((LAT_GLOBAL char*)b + lane_off));
 }
 // Store from the lanes with ok only (the cell base is pinned before the
 // lane mask is applied).
@@ -95,7 +99,8 @@ __device__ __forceinline__ void row_store_if(T* row, uint32_t cell_off,
                                              uint32_t lane_off, T v, bool ok) {
   char* b = (char*)row + cell_off;
   asm("" : "+s"(b));
-  if (ok) *(LAT_GLOBAL T*)((LAT_GLOBAL char*)b + lane_off) = v;
+  if (ok)
+    __builtin_nontemporal_store(v, (LAT_GLOBAL T*)((LAT_GLOBAL char*)b + lane_off));
 }
 
 }  // namespace lat
