@@ -81,26 +81,35 @@ __device__ __forceinline__ T row_load(const T* row, uint32_t cell_off,
   asm("" : "+s"(b));
   return *(const LAT_GLOBAL T*)((const LAT_GLOBAL char*)b + lane_off);
 }
-// The stores are non-temporal: a finished row is not read again by the
-// pass that writes it (measured on the 2D pass at 512^2 x 33^2: 1.9 %
-// shorter; non-temporal loads are 18 % longer, since neighbouring tiles
-// read overlapping source lines through the cache).
-template <typename T>
+// NT: non-temporal stores, for a pass whose output is too large to stay in
+// the caches for the next pass (the pass itself never reads a finished row
+// again).  Measured on the 2D pass at 512^2 x 33^2 (1.14 GB): 1.9 % shorter;
+// on a 76 MB state that the next kernel reads at once, longer.
+template <bool NT, typename T>
 __device__ __forceinline__ void row_store(T* row, uint32_t cell_off,
                                           uint32_t lane_off, T v) {
   char* b = (char*)row + cell_off;
   asm("" : "+s"(b));
-  __builtin_nontemporal_store(v, (LAT_GLOBAL T*)((LAT_GLOBAL char*)b + lane_off));
+  LAT_GLOBAL T* const q = (LAT_GLOBAL T*)((LAT_GLOBAL char*)b + lane_off);
+  if constexpr (NT)
+    __builtin_nontemporal_store(v, q);
+  else
+    *q = v;
 }
 // Store from the lanes with ok only (the cell base is pinned before the
 // lane mask is applied).
-template <typename T>
+template <bool NT, typename T>
 __device__ __forceinline__ void row_store_if(T* row, uint32_t cell_off,
                                              uint32_t lane_off, T v, bool ok) {
   char* b = (char*)row + cell_off;
   asm("" : "+s"(b));
-  if (ok)
-    __builtin_nontemporal_store(v, (LAT_GLOBAL T*)((LAT_GLOBAL char*)b + lane_off));
+  LAT_GLOBAL T* const q = (LAT_GLOBAL T*)((LAT_GLOBAL char*)b + lane_off);
+  if (ok) {
+    if constexpr (NT)
+      __builtin_nontemporal_store(v, q);
+    else
+      *q = v;
+  }
 }
 
 }  // namespace lat

@@ -244,7 +244,8 @@ constexpr int step2d_wgw() {
 // wrapping, so all cells of a row load from one uniform base plus one
 // per-lane offset (plus a uniform per-cell stride); otherwise each cell
 // keeps its own wrapped offset.
-template <typename T, int NV, int P, bool KOREN, bool INTERIOR, int WGW>
+template <typename T, int NV, int P, bool KOREN, bool INTERIOR, int WGW,
+          bool NT>
 __device__ __forceinline__ void step2d_tile(
     const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict__ u,
     T* __restrict__ stage, int nx, int ny, int shift, int xstep, int xoff0,
@@ -350,9 +351,9 @@ __device__ __forceinline__ void step2d_tile(
     v[KL] = last_in ? sb[KL * P * O::STRIDE] : T(0);
 #pragma unroll
     for (int k = 0; k < KL; ++k)
-      row_store(orow, (uint32_t)(k * P) * slot_bytes, flane, v[k]);
+      row_store<NT>(orow, (uint32_t)(k * P) * slot_bytes, flane, v[k]);
     __builtin_amdgcn_s_setprio(0);
-    row_store_if(orow, (uint32_t)(KL * P) * slot_bytes, flane, v[KL],
+    row_store_if<NT>(orow, (uint32_t)(KL * P) * slot_bytes, flane, v[KL],
                  last_in);
   };
   auto run_row = [&](auto steady, int t, const T (&c)[W],
@@ -362,7 +363,7 @@ __device__ __forceinline__ void step2d_tile(
       K::template row<decltype(steady)::value>(
           t, c, sin, sout, nxp, nxm, ay, beta, D, first, last, lane_l,
           lane_r, [&](int i, T v) {
-            row_store(orow, (uint32_t)i * slot_bytes, store_lane, v);
+            row_store<NT>(orow, (uint32_t)i * slot_bytes, store_lane, v);
           });
     } else {
       T* sb = sbase + (t & 1) * O::SIZE;
@@ -438,7 +439,7 @@ __device__ __forceinline__ void step2d_tile(
 // run the same row sequence (the staged stores synchronise them once
 // per row), so none may leave early; wavefronts past the end of the row
 // compute on duplicated sites and store nothing.
-template <typename T, int NV, int P, bool KOREN,
+template <typename T, int NV, int P, bool KOREN, bool NT,
           int WGW = step2d_wgw<T, NV, P>()>
 __global__ __launch_bounds__(64 * WGW) void k_step2d(
     const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict__ u,
@@ -458,11 +459,11 @@ __global__ __launch_bounds__(64 * WGW) void k_step2d(
   const bool interior = x0 + S <= nx && x0 - shift * H >= 0 &&
                         x0 + S - 1 + shift * H <= nx - 1;
   if (interior)
-    step2d_tile<T, NV, P, KOREN, true, WGW>(fin, fout, u, stage, nx, ny, shift,
+    step2d_tile<T, NV, P, KOREN, true, WGW, NT>(fin, fout, u, stage, nx, ny, shift,
                                        xstep, xoff0, ystep, yoff0,
                                        alpha_scale, beta, D, xg, w, y);
   else
-    step2d_tile<T, NV, P, KOREN, false, WGW>(fin, fout, u, stage, nx, ny, shift,
+    step2d_tile<T, NV, P, KOREN, false, WGW, NT>(fin, fout, u, stage, nx, ny, shift,
                                         xstep, xoff0, ystep, yoff0,
                                         alpha_scale, beta, D, xg, w, y);
 }
@@ -484,18 +485,27 @@ hipError_t launch_step2d_nv(const StepArgs& a, hipStream_t s) {
   const int ystep = a.shift % ny;
   const int yoff0 = (int)(((int64_t)a.shift * H) % ny);
   const T as = (T)a.alpha_scale, be = (T)a.beta, D = (T)a.D;
-  if (a.koren)
-    hipLaunchKernelGGL((k_step2d<T, NV, P, true>), dim3(nblocks),
-                       dim3(64 * WGW), 0,
-                       s, (const T*)a.fin, (T*)a.fout, (const T*)a.u, a.flag,
-                       nx, ny, a.shift, xstep, xoff0, ystep, yoff0, as, be, D,
-                       ngx, nblocks);
-  else
-    hipLaunchKernelGGL((k_step2d<T, NV, P, false>), dim3(nblocks),
-                       dim3(64 * WGW),
-                       0, s, (const T*)a.fin, (T*)a.fout, (const T*)a.u,
-                       a.flag, nx, ny, a.shift, xstep, xoff0, ystep, yoff0, as,
-                       be, D, ngx, nblocks);
+  // non-temporal stores when the state is larger than the 256 MB
+  // memory-side cache (the next pass cannot find it there anyway)
+  const bool nt = (uint64_t)NV * NV * (uint64_t)nx * (uint64_t)ny * sizeof(T) >
+                  (256ull << 20);
+  auto go = [&](auto kernel) {
+    hipLaunchKernelGGL(kernel, dim3(nblocks), dim3(64 * WGW), 0, s,
+                       (const T*)a.fin, (T*)a.fout, (const T*)a.u, a.flag, nx,
+                       ny, a.shift, xstep, xoff0, ystep, yoff0, as, be, D, ngx,
+                       nblocks);
+  };
+  if (a.koren) {
+    if (nt)
+      go(k_step2d<T, NV, P, true, true>);
+    else
+      go(k_step2d<T, NV, P, true, false>);
+  } else {
+    if (nt)
+      go(k_step2d<T, NV, P, false, true>);
+    else
+      go(k_step2d<T, NV, P, false, false>);
+  }
   return hipGetLastError();
 }
 
