@@ -562,7 +562,7 @@ def main():
                     choices=sorted(WORKLOADS))
     ap.add_argument("--scheme", default="koren", choices=["koren", "upwind"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--line-eps", type=float, default=1.8e-2,
+    ap.add_argument("--line-eps", type=float, default=2.4e-2,
                     help="coarse workload: faces whose stencil holds less "
                          "than this fraction of the site mass get no "
                          "learned correction (training keeps the same "
