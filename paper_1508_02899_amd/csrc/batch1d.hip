@@ -63,7 +63,7 @@ constexpr int parts_threads() {
 // items of a workgroup: the loads of the next tile are issued before the
 // current tile's columns are updated, so that they overlap its collision
 // and its stores.
-template <int NV, bool KOREN>
+template <int NV, bool KOREN, bool NT>
 __global__ __launch_bounds__(parts_threads<NV>()) void k_batch1d_parts(
     const float* __restrict__ fin, float* __restrict__ fout,
     const float* __restrict__ u, const BatchMember* __restrict__ mem,
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(parts_threads<NV>()) void k_batch1d_parts(
     issue(wn < ntiles ? wn : w, r, wn >= ntiles);
     PT::template collide<KOREN>(tile, alpha, m.nsub, m.beta, m.D);
     __syncthreads();
-    PT::store(tile, fout + m.f_off, m.nx, tl.x0);
+    PT::template store<NT>(tile, fout + m.f_off, m.nx, tl.x0);
     __syncthreads();  // the tile is refilled for the next work item
     w = wn;
   }
@@ -205,14 +205,22 @@ hipError_t launch_cap(const BatchLaunch& a, hipStream_t s) {
 template <int NV>
 hipError_t launch_parts(const BatchLaunch& a, hipStream_t s) {
   constexpr int WGW = BatchShape<NV>::WGW;
-  if (a.koren)
-    hipLaunchKernelGGL((k_batch1d_parts<NV, true>), dim3(a.grid),
-                       dim3(64 * WGW), 0, s, a.fin, a.fout, a.u, a.mem,
-                       a.tiles, a.ntiles, a.mflag, a.step_base, a.local_step);
-  else
-    hipLaunchKernelGGL((k_batch1d_parts<NV, false>), dim3(a.grid),
-                       dim3(64 * WGW), 0, s, a.fin, a.fout, a.u, a.mem,
-                       a.tiles, a.ntiles, a.mflag, a.step_base, a.local_step);
+  auto go = [&](auto kernel) {
+    hipLaunchKernelGGL(kernel, dim3(a.grid), dim3(64 * WGW), 0, s, a.fin,
+                       a.fout, a.u, a.mem, a.tiles, a.ntiles, a.mflag,
+                       a.step_base, a.local_step);
+  };
+  if (a.koren) {
+    if (a.nt)
+      go(k_batch1d_parts<NV, true, true>);
+    else
+      go(k_batch1d_parts<NV, true, false>);
+  } else {
+    if (a.nt)
+      go(k_batch1d_parts<NV, false, true>);
+    else
+      go(k_batch1d_parts<NV, false, false>);
+  }
   return hipGetLastError();
 }
 

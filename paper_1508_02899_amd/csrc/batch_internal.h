@@ -49,6 +49,7 @@ struct BatchLaunch {
   const int* mflag;
   const int* step_base;
   int local_step;
+  int nt;  // split-column tiles: non-temporal stores
 };
 
 hipError_t launch_batch1d(const BatchLaunch& a, hipStream_t s);

@@ -249,7 +249,11 @@ struct Parts1DTile {
     if (last) col[(W - 1) * STRIDE + SKEW] = c[W - 1];
   }
 
-  // 3. plane-by-plane stores of the finished tile
+  // 3. plane-by-plane stores of the finished tile; NT: non-temporal stores
+  // (for a launch whose output is too large to be found in the caches by
+  // the next one; a compile-time choice: a run-time branch between the two
+  // stores of one address is merged into one ordinary store)
+  template <bool NT = false>
   __device__ __forceinline__ static void store(const T* __restrict__ tile,
                                                T* __restrict__ fout, int nx,
                                                int x0) {
@@ -261,7 +265,13 @@ struct Parts1DTile {
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         const int j = fj0 + P * k;
-        if (k < K - 1 || j < NV) fout[(size_t)j * nx + ox] = tile[C::row(j) + fs];
+        if (k < K - 1 || j < NV) {
+          T* const q = &fout[(size_t)j * nx + ox];
+          if constexpr (NT)
+            __builtin_nontemporal_store(tile[C::row(j) + fs], q);
+          else
+            *q = tile[C::row(j) + fs];
+        }
       }
     }
   }
