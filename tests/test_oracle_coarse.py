@@ -106,6 +106,75 @@ def test_adam_first_step_is_sign_step():
     np.testing.assert_allclose(P["a"], [0.99, -1.99, 0.49], atol=1e-7)
 
 
+def test_divergence_matrix_hand_example():
+    """n = 2 by hand: unknowns x-face (row 0, k = 1), x-face (row 1, k = 1),
+    y-face (k = 1, column 0), y-face (k = 1, column 1); (D G)_J is the flux
+    out of cell J through its upper faces minus the flux into it through
+    its lower faces."""
+    D = C.divergence_matrix(2)
+    want = np.array([[1, 0, 1, 0],      # cell (jy, jx) = (0, 0)
+                     [-1, 0, 0, 1],     # (0, 1)
+                     [0, 1, -1, 0],     # (1, 0)
+                     [0, -1, 0, -1]])   # (1, 1)
+    np.testing.assert_array_equal(D, want)
+
+
+def check_corrected_site_hand_example(C):
+    """3 x 3 square c[jy, jx] = 1..9 (mass 45), stencil masses 1 (one face
+    0.01), line_eps 0.01 (threshold 0.45).  Face index: x-face (row a, face
+    k) = 2 a + k - 1; y-face (face k, column a) = 6 + 3 (k - 1) + a.  A
+    positive flux moves mass toward larger velocity index, a negative one
+    toward smaller; each face moves at most a quarter of its donor.
+      x (1, 1): +0.5 from (1,0) to (1,1), donor 4 -> not limited;
+      y (2, 2): -1.0 from (2,2) to (1,2), donor 9 -> not limited;
+      x (0, 2): +1.0 from (0,1) to (0,2), donor 2 -> limited to 0.5;
+      y (1, 0): -3.0 from (1,0) to (0,0), donor 4 -> limited to 1.0;
+      x (2, 1): stencil mass 0.01 < 0.45 -> no correction."""
+    nv = 3
+    c = np.arange(1.0, 10.0)
+    nf = 2 * nv * (nv - 1)
+    y = np.zeros(nf)
+    ms = np.ones(nf)
+    sg = np.ones(nf)
+    y[2], sg[2] = 0.5, 1.0
+    y[11], sg[11] = 1.0, -1.0
+    y[1], sg[1] = 1.0, 1.0
+    y[6], sg[6] = 3.0, -1.0
+    y[4], ms[4] = 70.0, 0.01
+    out = C.corrected_site(c, nv, y, ms, sg, line_eps=0.01)
+    want = np.array([[2.0, 1.5, 3.5],
+                     [2.5, 5.5, 7.0],
+                     [7.0, 8.0, 8.0]])
+    np.testing.assert_allclose(out.reshape(nv, nv), want, rtol=0,
+                               atol=1e-15)
+
+
+def check_corrected_site_closes_min_norm_targets(C):
+    """With y set to the least-norm face fluxes of f_true - f_pred divided by
+    sign x stencil mass, no face excluded and every flux below a quarter of
+    its donor, the corrected f_pred is f_true."""
+    rng = np.random.default_rng(11)
+    nv = 9
+    fp = 1.0 + rng.random(nv * nv)
+    ft = fp + 1e-3 * rng.standard_normal(nv * nv)
+    ft += (fp.sum() - ft.sum()) / ft.size
+    Gx, Gy = C.minnorm_fluxes((ft - fp).reshape(-1, 1), nv)
+    G = np.concatenate([Gx.reshape(-1), Gy.reshape(-1)])
+    _, ms, sg = C.face_features(fp, nv, 0.3, -0.2, 0.5, 0.1, 1.0, 2.0)
+    assert np.all(ms > 0) and np.abs(G).max() < 0.25
+    out = C.corrected_site(fp, nv, G / (sg * ms), ms, sg, line_eps=0.0)
+    np.testing.assert_allclose(out, ft, rtol=0, atol=1e-13)
+    assert np.abs(out - fp).max() > 1e-4    # the correction did something
+
+
+def test_corrected_site_hand_example():
+    check_corrected_site_hand_example(C)
+
+
+def test_corrected_site_closes_min_norm_targets():
+    check_corrected_site_closes_min_norm_targets(C)
+
+
 def test_corrected_site_conserves_mass_and_positivity():
     rng = np.random.default_rng(4)
     nv = 9
