@@ -210,6 +210,42 @@ def _torch():
     return torch
 
 
+def require_tensor(t, name, dtype, shape=None, numel=None, min_numel=None,
+                   ndim=None, cuda=True):
+    """Raise unless t is a contiguous CUDA tensor of the given dtype and
+    size.  Every pointer handed to the library passes through here first:
+    the kernels trust the sizes the descriptors imply, so a short, wrongly
+    typed or strided buffer must be refused before any launch.  Checks run
+    in the order type, dtype, contiguity, size, device."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} dtype {t.dtype} != {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if ndim is not None and t.dim() != ndim:
+        raise ValueError(f"{name} must have {ndim} dimensions, has {t.dim()}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} shape {tuple(t.shape)} != {tuple(shape)}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} holds {t.numel()} elements, needs {numel}")
+    if min_numel is not None and t.numel() < min_numel:
+        raise ValueError(
+            f"{name} holds {t.numel()} elements, needs at least {min_numel}")
+    if cuda and not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def require_cuda(**tensors):
+    """Raise unless every named tensor lives on the GPU (checked after the
+    sizes of all of them, so that a size error is reported first)."""
+    for name, t in tensors.items():
+        if t is not None and not t.is_cuda:
+            raise TypeError(f"{name} must be a CUDA tensor")
+
+
 class Lattice:
     """Handle over ``lattice_t``: owns the library's scratch buffer.
 
@@ -251,17 +287,9 @@ class Lattice:
             raise LatticeError(rc, msg)
         return rc
 
-    def _tensor_ptr(self, t, shape=None, name="tensor"):
-        torch = _torch()
-        if not isinstance(t, torch.Tensor) or not t.is_cuda:
-            raise TypeError(f"{name} must be a CUDA tensor")
-        if t.dtype != self.torch_dtype:
-            raise TypeError(f"{name} dtype {t.dtype} != {self.torch_dtype}")
-        if not t.is_contiguous():
-            raise ValueError(f"{name} must be contiguous")
-        if shape is not None and tuple(t.shape) != tuple(shape):
-            raise ValueError(f"{name} shape {tuple(t.shape)} != {tuple(shape)}")
-        return ctypes.c_void_p(t.data_ptr())
+    def _tensor_ptr(self, t, shape=None, name="tensor", cuda=True):
+        return require_tensor(t, name, self.torch_dtype, shape=shape,
+                              cuda=cuda)
 
     # -- API -------------------------------------------------------------
     def step(self, f, u, tau_p: float, kappa: float, dt: float, nsteps: int,
@@ -270,24 +298,25 @@ class Lattice:
 
         u holds one or more slices ([slices, dim, ny, nx] or
         [slices, 1, nx] in 1D)."""
-        return self._advance(self.lib.lattice_step, f, u, tau_p, kappa, dt,
-                             nsteps, check)
+        return self._advance("lattice_step", f, u, tau_p, kappa, dt, nsteps,
+                             check)
 
     def collide(self, f, u, tau_p: float, kappa: float, dt: float,
                 nsteps: int = 1, check: bool = True):
         """The collision part of step() alone (no streaming, no learned
         correction)."""
-        return self._advance(self.lib.lattice_collide, f, u, tau_p, kappa, dt,
+        return self._advance("lattice_collide", f, u, tau_p, kappa, dt,
                              nsteps, check)
 
     def _advance(self, fn, f, u, tau_p, kappa, dt, nsteps, check):
         s = self.spec
-        fp = self._tensor_ptr(f, s.state_shape, "f")
+        fp = self._tensor_ptr(f, s.state_shape, "f", cuda=False)
         per = s.dim * s.nx * (s.ny if s.dim == 2 else 1)
-        if u.numel() % per:
+        up = self._tensor_ptr(u, None, "u", cuda=False)
+        if u.numel() % per or u.numel() == 0:
             raise ValueError("u is not a whole number of slices")
-        up = self._tensor_ptr(u, None, "u")
-        rc = fn(self._L, fp, up, u.numel() // per, float(tau_p), float(kappa),
+        require_cuda(f=f, u=u)
+        rc = getattr(self.lib, fn)(self._L, fp, up, u.numel() // per, float(tau_p), float(kappa),
                 float(dt), int(nsteps))
         if check:
             self._check(rc)
@@ -295,9 +324,9 @@ class Lattice:
 
     def moments(self, f, dt: float) -> dict:
         """FP64 mass / momentum / second moment / variance (synchronous)."""
+        fp = self._tensor_ptr(f, self.spec.state_shape, "f")
         m = Moments()
-        rc = self.lib.lattice_moments(self._L, self._tensor_ptr(f, None, "f"),
-                                      float(dt), ctypes.byref(m))
+        rc = self.lib.lattice_moments(self._L, fp, float(dt), ctypes.byref(m))
         out = {
             "mass": m.mass,
             "momentum": list(m.momentum)[: self.spec.dim],
@@ -314,11 +343,11 @@ class Lattice:
         """rho(x) = dv^dim sum_j f as a new FP64 CUDA tensor [ny, nx]."""
         torch = _torch()
         s = self.spec
+        fp = self._tensor_ptr(f, s.state_shape, "f")
         rho = torch.empty((s.ny if s.dim == 2 else 1, s.nx),
                           dtype=torch.float64, device=f.device)
-        self._check(self.lib.lattice_density(
-            self._L, self._tensor_ptr(f, None, "f"), float(dt),
-            ctypes.c_void_p(rho.data_ptr())))
+        self._check(self.lib.lattice_density(self._L, fp, float(dt),
+                                             ctypes.c_void_p(rho.data_ptr())))
         return rho
 
     def flow_from_modes(self, coef, out=None):
@@ -328,20 +357,22 @@ class Lattice:
         [slices, 1, nx] (1D) in the lattice dtype."""
         torch = _torch()
         s = self.spec
-        assert coef.dtype == torch.float32 and coef.is_cuda
-        assert coef.is_contiguous() and coef.shape[-1] == 2
+        require_tensor(coef, "coef", torch.float32, ndim=3 if s.dim == 1 else 4)
+        if coef.shape[-1] != 2:
+            raise ValueError("coef must end in (cos, sin) pairs")
+        if s.dim == 2 and coef.shape[1] != 2 * (coef.shape[2] - 1) + 1:
+            raise ValueError("2D coef must be [slices, 2K+1, K+1, 2]")
         ns = coef.shape[0]
         dt = torch.float64 if s.dtype == "f64" else torch.float32
         shape = (ns, 2, s.ny, s.nx) if s.dim == 2 else (ns, 1, s.nx)
         if out is None:
             out = torch.empty(shape, dtype=dt, device=coef.device)
-        assert tuple(out.shape) == shape and out.dtype == dt
+        require_tensor(out, "out", dt, shape=shape)
         if s.dim == 1:
             rc = self.lib.lattice_flow1d_modes(self._L, coef.shape[1],
                                                _ptr(coef), ns, _ptr(out))
         else:
             K = coef.shape[2] - 1
-            assert coef.shape[1] == 2 * K + 1
             rc = self.lib.lattice_flow2d_modes(self._L, K, _ptr(coef), ns,
                                                _ptr(out))
         self._check(rc)
@@ -363,9 +394,9 @@ class Lattice:
         """<rho_r^2> on tilings r = 2^k sites, k < levels (numpy array),
         from an FP64 density tensor such as density() returns."""
         import numpy as np
-        assert rho.dtype == _torch().float64 and rho.is_cuda
-        assert rho.is_contiguous() and rho.numel() == self.spec.nx * (
-            self.spec.ny if self.spec.dim == 2 else 1)
+        require_tensor(rho, "rho", _torch().float64,
+                       numel=self.spec.nx * (self.spec.ny
+                                             if self.spec.dim == 2 else 1))
         out = np.empty(levels, dtype=np.float64)
         self._check(self.lib.lattice_rho_r2(
             self._L, ctypes.c_void_p(rho.data_ptr()), int(levels),
@@ -376,16 +407,20 @@ class Lattice:
         """(CFL of Eq. 3, kappa dt_s / dv^2 of Eq. 4) for the slices in u."""
         s = self.spec
         per = s.dim * s.nx * (s.ny if s.dim == 2 else 1)
+        up = self._tensor_ptr(u, None, "u")
+        if u.numel() % per or u.numel() == 0:
+            raise ValueError("u is not a whole number of slices")
         out = (ctypes.c_double * 2)()
         self._check(self.lib.lattice_stability(
-            self._L, self._tensor_ptr(u, None, "u"), u.numel() // per,
+            self._L, up, u.numel() // per,
             float(tau_p), float(kappa), float(dt), out))
         return out[0], out[1]
 
     def copy_state(self, dst, src):
-        self._check(self.lib.lattice_copy_state(
-            self._L, self._tensor_ptr(dst, self.spec.state_shape, "dst"),
-            self._tensor_ptr(src, self.spec.state_shape, "src")))
+        dp = self._tensor_ptr(dst, self.spec.state_shape, "dst", cuda=False)
+        sp = self._tensor_ptr(src, self.spec.state_shape, "src", cuda=False)
+        require_cuda(dst=dst, src=src)
+        self._check(self.lib.lattice_copy_state(self._L, dp, sp))
 
     def sync(self, check: bool = True) -> int:
         rc = self.lib.lattice_sync(self._L)
@@ -507,17 +542,24 @@ class Batch:
 
     def step(self, f, u, nsteps: int, graph_steps: int = 0):
         """Advance every member by nsteps (asynchronous); graph_steps > 0
-        replays a captured HIP graph of that many (even) steps."""
+        replays a captured HIP graph of that many (even) steps.  f: packed
+        FP32 state of total_cells elements; u: packed FP32 flows of at
+        least total_u elements."""
+        torch = _torch()
+        fp = require_tensor(f, "f", torch.float32, numel=self.total_cells,
+                            cuda=False)
+        up = require_tensor(u, "u", torch.float32, min_numel=self.total_u,
+                            cuda=False)
+        require_cuda(f=f, u=u)
         self._check(self.lib.lattice_batch_step(
-            self._B, ctypes.c_void_p(f.data_ptr()),
-            ctypes.c_void_p(u.data_ptr()), int(nsteps),
-            1 if graph_steps else 0, int(graph_steps)))
+            self._B, fp, up, int(nsteps), 1 if graph_steps else 0,
+            int(graph_steps)))
 
     def moments(self, f):
         import numpy as np
+        fp = require_tensor(f, "f", _torch().float32, numel=self.total_cells)
         out = (ctypes.c_double * (6 * len(self.members)))()
-        self._check(self.lib.lattice_batch_moments(
-            self._B, ctypes.c_void_p(f.data_ptr()), out))
+        self._check(self.lib.lattice_batch_moments(self._B, fp, out))
         return np.array(out).reshape(len(self.members), 6)
 
     def sync(self, check: bool = True):
@@ -549,7 +591,13 @@ def restrict(f_fine, dim: int, stream=None):
     f_fine [nv_f^dim, ...] FP32 CUDA tensor; returns a new coarse tensor."""
     torch = _torch()
     L = load_library()
-    nvf = int(round(f_fine.shape[0] ** (1.0 / dim)))
+    if dim not in (1, 2):
+        raise ValueError("dim must be 1 or 2")
+    require_tensor(f_fine, "f_fine", torch.float32, cuda=False)
+    nvf = int(round(f_fine.shape[0] ** (1.0 / dim))) if f_fine.dim() else 0
+    if nvf < 5 or nvf ** dim != f_fine.shape[0] or (nvf - 1) % 4:
+        raise ValueError("f_fine must be [nv_f^dim, ...] with nv_f = 4k + 1")
+    require_cuda(f_fine=f_fine)
     nvc = (nvf - 1) // 4 + 1
     sites = f_fine.numel() // f_fine.shape[0]
     out = torch.empty((nvc ** dim,) + tuple(f_fine.shape[1:]),
@@ -595,35 +643,78 @@ class Mlp:
             self._M, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
         return a
 
+    @staticmethod
+    def _samples_ptrs(X, t=None, w=None):
+        """Pointers of a sample set: X [n, 8], t [n], w [n], FP32 CUDA."""
+        torch = _torch()
+        require_tensor(X, "X", torch.float32, ndim=2, cuda=False)
+        n = X.shape[0]
+        if X.shape[1] != 8:
+            raise ValueError(f"X must be [n, 8], is {tuple(X.shape)}")
+        ptrs = [_ptr(X)]
+        for name, v in (("t", t), ("w", w)):
+            if v is not None:
+                ptrs.append(require_tensor(v, name, torch.float32, numel=n,
+                                           cuda=False))
+        require_cuda(X=X, t=t, w=w)
+        return n, ptrs
+
     def grad(self, X, t, w):
         torch = _torch()
+        n, (xp, tp, wp) = self._samples_ptrs(X, t, w)
         g = torch.empty(MLP_NPARAMS, dtype=torch.float32, device=X.device)
         loss = ctypes.c_double()
-        self._check(self.lib.lattice_mlp_grad(self._M, _ptr(X), _ptr(t), _ptr(w),
-                                              t.numel(), _ptr(g),
+        self._check(self.lib.lattice_mlp_grad(self._M, xp, tp, wp, n, _ptr(g),
                                               ctypes.byref(loss)))
         return loss.value, g
 
     def train(self, X, t, w, batch: int, steps: int, lr: float):
+        n, (xp, tp, wp) = self._samples_ptrs(X, t, w)
         loss = ctypes.c_double()
-        self._check(self.lib.lattice_mlp_train(self._M, _ptr(X), _ptr(t),
-                                               _ptr(w), t.numel(), int(batch),
-                                               int(steps), float(lr),
-                                               ctypes.byref(loss)))
+        self._check(self.lib.lattice_mlp_train(self._M, xp, tp, wp, n,
+                                               int(batch), int(steps),
+                                               float(lr), ctypes.byref(loss)))
         return loss.value
 
     def forward(self, X):
         torch = _torch()
-        n = X.shape[0]
+        n, (xp,) = self._samples_ptrs(X)
         y = torch.empty(n, dtype=torch.float32, device=X.device)
-        self._check(self.lib.lattice_mlp_forward(self._M, _ptr(X), n, _ptr(y)))
+        self._check(self.lib.lattice_mlp_forward(self._M, xp, n, _ptr(y)))
         return y
+
+    @staticmethod
+    def _sites_ptr(sites, nsites):
+        """Site indices: int32 CUDA tensor with every value in [0, nsites)
+        (the sample kernels index the state with them)."""
+        torch = _torch()
+        require_tensor(sites, "sites", torch.int32, ndim=1, cuda=False)
+        if sites.numel() == 0:
+            raise ValueError("sites is empty")
+        lo, hi = int(sites.min()), int(sites.max())
+        if lo < 0 or hi >= nsites:
+            raise ValueError(f"site indices must lie in [0, {nsites}), "
+                             f"got [{lo}, {hi}]")
+        return require_tensor(sites, "sites", torch.int32)
 
     def samples(self, lat, dt, tau_p, St, f_pred, f_true, u, sites,
                 rel_eps: float = 0.0):
         """Training samples at the given sites (int32 CUDA tensor); faces
         with stencil mass below rel_eps x site mass get zero weight."""
         torch = _torch()
+        s = lat.spec
+        if s.dim != 2 or s.nv != 17 or s.dtype != "f32":
+            raise ValueError("samples need a 2D FP32 lattice of 17^2 "
+                             "velocities")
+        nsites = s.nx * s.ny
+        pp = require_tensor(f_pred, "f_pred", torch.float32,
+                            shape=s.state_shape, cuda=False)
+        tp = require_tensor(f_true, "f_true", torch.float32,
+                            shape=s.state_shape, cuda=False)
+        up = require_tensor(u, "u", torch.float32, min_numel=2 * nsites,
+                            cuda=False)
+        require_cuda(f_pred=f_pred, f_true=f_true, u=u)
+        sp = self._sites_ptr(sites, nsites)
         nf = 544
         n = sites.numel() * nf
         X = torch.empty((n, 8), dtype=torch.float32, device=f_pred.device)
@@ -631,9 +722,7 @@ class Mlp:
         w = torch.empty(n, dtype=torch.float32, device=f_pred.device)
         self._check(self.lib.lattice_mlp_samples(
             lat._L, float(dt), float(tau_p), float(St), float(rel_eps),
-            _ptr(f_pred),
-            _ptr(f_true), _ptr(u), _ptr(sites), sites.numel(), _ptr(X),
-            _ptr(t), _ptr(w)))
+            pp, tp, up, sp, sites.numel(), _ptr(X), _ptr(t), _ptr(w)))
         return X, t, w
 
     def samples_natural(self, fine, lat, dt, tau_p, kappa, St, f_fine,
@@ -642,6 +731,23 @@ class Mlp:
         f_fine = the fine state after streaming (before its collision),
         f_pred = the coarse collision of its restriction (lattice lat)."""
         torch = _torch()
+        s, sf = lat.spec, fine.spec
+        if s.dim != 2 or s.nv != 17 or s.dtype != "f32":
+            raise ValueError("samples need a 2D FP32 lattice of 17^2 "
+                             "velocities")
+        if (sf.dim, sf.nx, sf.ny, sf.nv, sf.dtype) != (2, s.nx, s.ny, 65,
+                                                       "f32"):
+            raise ValueError("the fine lattice must be 2D FP32 65^2 on the "
+                             "same sites")
+        nsites = s.nx * s.ny
+        fp = require_tensor(f_fine, "f_fine", torch.float32,
+                            shape=sf.state_shape, cuda=False)
+        pp = require_tensor(f_pred, "f_pred", torch.float32,
+                            shape=s.state_shape, cuda=False)
+        up = require_tensor(u, "u", torch.float32, min_numel=2 * nsites,
+                            cuda=False)
+        require_cuda(f_fine=f_fine, f_pred=f_pred, u=u)
+        sp = self._sites_ptr(sites, nsites)
         nf = 544
         n = sites.numel() * nf
         X = torch.empty((n, 8), dtype=torch.float32, device=f_pred.device)
@@ -649,8 +755,8 @@ class Mlp:
         w = torch.empty(n, dtype=torch.float32, device=f_pred.device)
         self._check(self.lib.lattice_mlp_samples_natural(
             fine._L, lat._L, float(dt), float(tau_p), float(kappa), float(St),
-            float(rel_eps), _ptr(f_fine), _ptr(f_pred), _ptr(u), _ptr(sites),
-            sites.numel(), _ptr(X), _ptr(t), _ptr(w)))
+            float(rel_eps), fp, pp, up, sp, sites.numel(), _ptr(X), _ptr(t),
+            _ptr(w)))
         return X, t, w
 
     def attach(self, lat, St: float, line_eps: float = 1e-4):
@@ -695,5 +801,6 @@ def velocity(spec: LatticeSpec, dt: float):
 
 
 __all__ = ["Lattice", "LatticeSpec", "LatticeError", "LatticeLibraryMissing",
+           "require_tensor", "require_cuda",
            "Batch", "Member", "Mlp", "restrict", "load_library", "strerror",
            "velocity", "EXPORTS", "MLP_NPARAMS"]
