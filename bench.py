@@ -497,8 +497,15 @@ def summarize(args):
     ny = w["n"] if w["dim"] == 2 else 1
     sites = w["n"] * ny
     cells = sites * w["nv"] ** w["dim"]
-    state = cells * elem
-    algo = 2 * state + w["dim"] * sites * elem
+    algo = 2 * cells * elem + w["dim"] * sites * elem
+    # the copy kernel moves the whole span of the state (its padding too)
+    from paper_1508_02899_amd import LatticeSpec
+    from paper_1508_02899_amd.lattice import recommended_pitch
+    spec = LatticeSpec(dim=w["dim"], nx=w["n"], ny=ny, nv=w["nv"], dx=1.0,
+                       dtype=w["dtype"])
+    if not args.contiguous:
+        spec.plane_pitch = recommended_pitch(spec)
+    state = spec.state_span * elem
     name = f"{kern}_{args.workload}"
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     cmd = args.command or "(command not recorded)"
@@ -575,6 +582,10 @@ def main():
                     help="device: synthesise the flow slices on the GPU from "
                          "their Fourier mode tables inside the timed region "
                          "(no prestaged u; 2D workloads)")
+    ap.add_argument("--contiguous", action="store_true",
+                    help="keep the velocity planes of the state contiguous "
+                         "(plane pitch nx*ny) instead of the padded pitch "
+                         "the library recommends")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="N",
                     help="after the timed region, launch the plain state "
                          "copy kernel N times on a state-sized buffer (a "
@@ -606,6 +617,7 @@ def main():
     import torch
 
     from paper_1508_02899_amd import Lattice, LatticeSpec, inputs
+    from paper_1508_02899_amd.lattice import recommended_pitch
 
     w = WORKLOADS[args.workload]
     if args.st is not None:
@@ -634,8 +646,14 @@ def main():
     f0 = inputs.gaussian_ic(dim, n, nv, dx, dv, ny=ny, dtype=npdt)
     spec = LatticeSpec(dim=dim, nx=n, ny=ny, nv=nv, dx=dx, vstride=w["s"],
                        scheme=args.scheme, dtype=w["dtype"], u_hold=1)
+    if not args.contiguous:
+        # velocity planes padded as the library recommends (a 512^2 FP32
+        # plane is 1 MiB: without padding the planes one step touches
+        # together share HBM channels)
+        spec.plane_pitch = recommended_pitch(spec)
     lat = Lattice(spec)
-    f = torch.from_numpy(f0).cuda()
+    f = spec.state_from(f0)
+    del f0
     if device_flow:
         # mode tables only (host RNG, a few MB); slices made on the device
         tab = torch.from_numpy(inputs.flow2d_modes(
@@ -664,9 +682,7 @@ def main():
     nsub = max(1, math.ceil(cfl / bound))
     if nsub > 1:
         lat.close()
-        spec = LatticeSpec(dim=dim, nx=n, ny=ny, nv=nv, dx=dx,
-                           vstride=w["s"], scheme=args.scheme,
-                           dtype=w["dtype"], u_hold=1, nsub=nsub)
+        spec = replace(spec, nsub=nsub)
         lat = Lattice(spec)
         cfl, dnum = lat.stability(u, tau_p, w["kappa"], dt)
     log(f"bench: nsub {nsub}, CFL {cfl:.3f}, kappa dt/dv^2 {dnum:.2e}")
@@ -705,7 +721,7 @@ def main():
     # reading and writing the whole state; a 1D step is one launch
     kern_ms, launches = ev2.elapsed_time(ev3), K * (nsub if dim == 2 else 1)
     if args.copy_calibration:
-        g = torch.empty_like(f)
+        g = spec.empty_state()
         lat.copy_state(g, f)
         lat.sync()
         t1 = time.perf_counter()
@@ -751,6 +767,7 @@ def main():
                             "inside the timed region" if device_flow else
                             ", flow prestaged in HBM")),
             "cells": cells,
+            "plane_pitch": spec.pitch,
             "scheme": args.scheme,
             "nsub": nsub,
             "cfl": round(cfl, 4),

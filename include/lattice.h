@@ -62,12 +62,22 @@ enum {
 };
 
 /*
- * Lattice description.  Layouts (all contiguous, x fastest):
- *   f : [nv^dim][ny][nx]   velocity plane jv = jy*nv + jx in 2D (jv = j in
- *                          1D, ny = 1); dtype elements;
- *   u : [slices][dim][ny][nx]  fluid velocity components, dtype elements.
+ * Lattice description.  Layouts (x fastest):
+ *   f : nv^dim velocity planes, plane jv = jy*nv + jx in 2D (jv = j in 1D,
+ *       ny = 1); each plane is [ny][nx] contiguous dtype elements and plane
+ *       jv starts plane_pitch*jv elements after plane 0 (plane_pitch = 0
+ *       means nx*ny: the whole state is contiguous [nv^dim][ny][nx]).  The
+ *       plane_pitch - nx*ny elements after each plane are never read as
+ *       state and never written in f (whole-state copies may carry them
+ *       through the library's own buffers);
+ *   u : [slices][dim][ny][nx]  fluid velocity components, contiguous, dtype
+ *       elements.
+ * Why a pitch: when the plane size is a multiple of a large power of two
+ * (512 x 512 FP32 sites: 1 MiB), the same site of the velocity planes that
+ * one step touches together falls on the same HBM channels; a few hundred
+ * bytes of padding per plane spreads them (lattice_plane_pitch).
  * Limits: nx*ny*nv^dim*sizeof(dtype) < 2^40 and
- * nv^(dim-1)*nx*ny*sizeof(dtype) < 2^31 (one row of velocity planes).
+ * nv^(dim-1)*plane_pitch*sizeof(dtype) < 2^31 (one row of velocity planes).
  * Compiled velocity lattices: 1D any odd nv in [3, 129] (FP32) or [3, 65]
  * (FP64); 2D odd nv in [3, 21], 25, 33, 65 (FP32) and 3, 5, 9, 17, 33
  * (FP64).  Other odd nv >= 3 give LATTICE_ENOTSUP.
@@ -85,6 +95,9 @@ typedef struct {
   int64_t u_hold;  /* steps per u slice within one lattice_step call;
                       0 = a single slice for the whole call */
   void* stream;    /* hipStream_t to run on; NULL = the default stream */
+  int64_t plane_pitch; /* elements from one velocity plane of f to the next;
+                          0 = nx*ny (contiguous); else >= nx*ny.  1D: 0 or
+                          nx only */
 } lattice_desc;
 
 /* Moments of f (Sec. 3.2 mass normalisation and its velocity moments):
@@ -101,8 +114,16 @@ typedef struct {
 } lattice_moments_t;
 
 /* Fill *d with defaults: dim 1, nx 1, ny 1, nv 33, vstride 1, dx 1, Koren,
- * FP32, nsub 1, u_hold 0, default stream.  EINVAL if d is NULL. */
+ * FP32, nsub 1, u_hold 0, default stream, plane_pitch 0 (contiguous).
+ * EINVAL if d is NULL. */
 int lattice_desc_default(lattice_desc* d);
+
+/* The plane pitch this library recommends for the lattice *d (its
+ * plane_pitch field is ignored): nx*ny, or, when one plane of the state
+ * spans a multiple of 64 KiB, nx*ny plus 64 elements, which keeps the
+ * velocity planes that one step reads and writes together off the same HBM
+ * channels.  1D lattices: nx.  Host-only; EINVAL on a bad descriptor. */
+int lattice_plane_pitch(const lattice_desc* d, int64_t* pitch);
 
 /* Velocity geometry for a time step dt: *dv = vstride dx / dt,
  * *vmax = h dv.  Host-only; EINVAL on a bad descriptor or dt <= 0. */
@@ -113,8 +134,10 @@ int lattice_velocity(const lattice_desc* d, double dt, double* dv,
  * Validate *d and create a handle that owns a device scratch buffer of the
  * state's size (the ping-pong twin of f) plus small reduction buffers.
  * EINVAL: dim not 1/2, nx/ny < 1, nv even or < 3, vstride < 1, dx <= 0,
- * scheme/dtype unknown, nsub < 1, u_hold < 0, out NULL, sizes past the
- * limits; ENOTSUP: 2D nv without a compiled kernel; ENOMEM; EHIP.
+ * scheme/dtype unknown, nsub < 1, u_hold < 0, plane_pitch negative, below
+ * nx*ny or (1D) other than nx, out NULL, sizes past the limits; ENOTSUP:
+ * 2D nv without a compiled kernel; ENOMEM; EHIP.  The scratch twin has the
+ * same plane pitch as f.
  */
 int lattice_init(const lattice_desc* d, lattice_t** out);
 

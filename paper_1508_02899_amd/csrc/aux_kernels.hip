@@ -49,11 +49,12 @@ struct Vec16<double> {
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_plane_sums(const T* __restrict__ f,
                                                        int64_t sites,
+                                                       int64_t pitch,
                                                        double* __restrict__ out) {
   __shared__ double sh[kBlock];
   using V = typename Vec16<T>::type;
   constexpr int NE = Vec16<T>::n;
-  const T* p = f + (size_t)blockIdx.x * (size_t)sites;
+  const T* p = f + (size_t)blockIdx.x * (size_t)pitch;
   double acc = 0.0;
   if (sites % NE == 0 && ((uintptr_t)p & 15) == 0) {  // uniform
     const V* q = reinterpret_cast<const V*>(p);
@@ -80,7 +81,7 @@ __global__ __launch_bounds__(kBlock) void k_plane_sums(const T* __restrict__ f,
 // sum_k Q_k/M - |P/M|^2.  Single workgroup, fixed order.
 __global__ __launch_bounds__(kBlock) void k_moments_final(
     const double* __restrict__ ps, int nv, int dim, double w, double dv,
-    double* __restrict__ out) {
+    const int* __restrict__ flag, double* __restrict__ out) {
   __shared__ double sh[kBlock];
   const int h = (nv - 1) / 2;
   const int nplanes = dim == 1 ? nv : nv * nv;
@@ -108,19 +109,21 @@ __global__ __launch_bounds__(kBlock) void k_moments_final(
     out[4] = w * qy;
     const double var = (qx + qy) / m - ((px / m) * (px / m) + (py / m) * (py / m));
     out[5] = var;
+    out[6] = (double)*flag;
   }
 }
 
 // rho[site] = dvd * sum_j f[j][site], FP64, j in order.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_density(const T* __restrict__ f,
-                                                    int64_t sites, int nplanes,
+                                                    int64_t sites,
+                                                    int64_t pitch, int nplanes,
                                                     double dvd,
                                                     double* __restrict__ rho) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= sites) return;
   double acc = 0.0;
-  for (int j = 0; j < nplanes; ++j) acc += (double)f[(size_t)j * sites + i];
+  for (int j = 0; j < nplanes; ++j) acc += (double)f[(size_t)j * pitch + i];
   rho[i] = dvd * acc;
 }
 
@@ -196,30 +199,32 @@ int grid_for(int64_t n) {
 
 }  // namespace
 
-hipError_t launch_moments(const void* f, int64_t sites, int nv, int dim,
-                          int f64, double w, double dv, double* plane_sums,
-                          double* out, hipStream_t s) {
+hipError_t launch_moments(const void* f, int64_t sites, int64_t pitch,
+                          int nv, int dim, int f64, double w, double dv,
+                          double* plane_sums, const int* flag, double* out,
+                          hipStream_t s) {
   const int nplanes = dim == 1 ? nv : nv * nv;
   if (f64)
     hipLaunchKernelGGL(k_plane_sums<double>, dim3(nplanes), dim3(kBlock), 0, s,
-                       (const double*)f, sites, plane_sums);
+                       (const double*)f, sites, pitch, plane_sums);
   else
     hipLaunchKernelGGL(k_plane_sums<float>, dim3(nplanes), dim3(kBlock), 0, s,
-                       (const float*)f, sites, plane_sums);
+                       (const float*)f, sites, pitch, plane_sums);
   hipLaunchKernelGGL(k_moments_final, dim3(1), dim3(kBlock), 0, s, plane_sums,
-                     nv, dim, w, dv, out);
+                     nv, dim, w, dv, flag, out);
   return hipGetLastError();
 }
 
-hipError_t launch_density(const void* f, int64_t sites, int nplanes, int f64,
-                          double dvd, double* rho, hipStream_t s) {
+hipError_t launch_density(const void* f, int64_t sites, int64_t pitch,
+                          int nplanes, int f64, double dvd, double* rho,
+                          hipStream_t s) {
   const int g = (int)((sites + kBlock - 1) / kBlock);
   if (f64)
     hipLaunchKernelGGL(k_density<double>, dim3(g), dim3(kBlock), 0, s,
-                       (const double*)f, sites, nplanes, dvd, rho);
+                       (const double*)f, sites, pitch, nplanes, dvd, rho);
   else
     hipLaunchKernelGGL(k_density<float>, dim3(g), dim3(kBlock), 0, s,
-                       (const float*)f, sites, nplanes, dvd, rho);
+                       (const float*)f, sites, pitch, nplanes, dvd, rho);
   return hipGetLastError();
 }
 

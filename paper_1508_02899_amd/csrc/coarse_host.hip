@@ -138,7 +138,8 @@ int lattice_mlp_samples(lattice_t* L, double dt, double tau_p, double St,
       !(St > 0) || !(rel_eps >= 0) || !(rel_eps < 1))
     return LATTICE_EINVAL;
   const lattice_desc& d = L->d;
-  if (d.dim != 2 || d.nv != 17 || d.dtype != LATTICE_F32)
+  if (d.dim != 2 || d.nv != 17 || d.dtype != LATTICE_F32 ||
+      L->pitch != L->sites)  // the network kernels read contiguous states
     return LATTICE_ENOTSUP;
   lat::CoarseGeom g;
   g.nx = (int)d.nx;
@@ -169,7 +170,8 @@ int lattice_mlp_samples_natural(const lattice_t* fine, lattice_t* L,
   const lattice_desc& d = L->d;
   const lattice_desc& e = fine->d;
   if (d.dim != 2 || d.nv != 17 || d.dtype != LATTICE_F32 || e.dim != 2 ||
-      e.nv != 65 || e.dtype != LATTICE_F32)
+      e.nv != 65 || e.dtype != LATTICE_F32 || L->pitch != L->sites ||
+      fine->pitch != fine->sites)  // the network kernels read contiguous states
     return LATTICE_ENOTSUP;
   if (e.nx != d.nx || e.ny != d.ny || e.dx != d.dx ||
       d.vstride != 4 * e.vstride)
@@ -277,7 +279,8 @@ int lattice_mlp_attach(lattice_t* L, lattice_mlp_t* M, double St,
     L->mlp = nullptr;
     return LATTICE_OK;
   }
-  if (L->d.dim != 2 || L->d.nv != 17 || L->d.dtype != LATTICE_F32)
+  if (L->d.dim != 2 || L->d.nv != 17 || L->d.dtype != LATTICE_F32 ||
+      L->pitch != L->sites)
     return LATTICE_ENOTSUP;
   if (!(St > 0) || !(line_eps >= 0)) return LATTICE_EINVAL;
   L->mlp = M;

@@ -51,11 +51,22 @@ bool bad_desc(const lattice_desc* d) {
   const double elem = d->dtype == LATTICE_F64 ? 8.0 : 4.0;
   const double ny = d->dim == 2 ? (double)d->ny : 1.0;
   const double sites = (double)d->nx * ny;
-  const double row = sites * (d->dim == 2 ? (double)d->nv : 1.0) * elem;
-  const double total = sites * pow((double)d->nv, d->dim) * elem;
-  if (row >= 2147483648.0 || total >= 1099511627776.0) return true;
   if (d->nx >= 2147483647 || ny >= 2147483647) return true;
+  if (d->plane_pitch < 0) return true;
+  if (d->plane_pitch != 0 && (double)d->plane_pitch < sites) return true;
+  if (d->dim == 1 && d->plane_pitch != 0 && d->plane_pitch != d->nx)
+    return true;
+  const double pitch = d->plane_pitch ? (double)d->plane_pitch : sites;
+  const double row = pitch * (d->dim == 2 ? (double)d->nv : 1.0) * elem;
+  const double total = pitch * pow((double)d->nv, d->dim) * elem;
+  if (row >= 2147483648.0 || total >= 1099511627776.0) return true;
   return false;
+}
+
+// Element pitch between velocity planes of a valid descriptor.
+int64_t plane_pitch_of(const lattice_desc& d) {
+  const int64_t sites = d.nx * (d.dim == 2 ? d.ny : 1);
+  return d.plane_pitch ? d.plane_pitch : sites;
 }
 
 // Drift bound of Eq. 3 for the scheme: strict CFL < 1 for upwind; CFL <= 1/2
@@ -115,6 +126,26 @@ int lattice_desc_default(lattice_desc* d) {
   return LATTICE_OK;
 }
 
+int lattice_plane_pitch(const lattice_desc* d, int64_t* pitch) {
+  if (!pitch) return LATTICE_EINVAL;
+  if (!d) return LATTICE_EINVAL;
+  lattice_desc c = *d;
+  c.plane_pitch = 0;
+  if (bad_desc(&c)) return LATTICE_EINVAL;
+  const int64_t sites = c.nx * (c.dim == 2 ? c.ny : 1);
+  const int64_t elem = c.dtype == LATTICE_F64 ? 8 : 4;
+  int64_t p = sites;
+  // 64 elements (256 B in FP32) after every plane whose size is a multiple
+  // of 64 KiB: the copy of the step's access pattern at 512^2 x 33^2 runs
+  // about 9 % faster with any pad of 32..192 elements, and 64 keeps every
+  // plane 256-byte aligned
+  if (c.dim == 2 && (sites * elem) % 65536 == 0) p = sites + 64;
+  c.plane_pitch = p;
+  if (bad_desc(&c)) p = sites;  // the padded row would pass the limits
+  *pitch = p;
+  return LATTICE_OK;
+}
+
 int lattice_velocity(const lattice_desc* d, double dt, double* dv,
                      double* vmax) {
   if (bad_desc(d) || !(dt > 0.0) || !isfinite(dt) || !dv || !vmax)
@@ -141,9 +172,11 @@ int lattice_init(const lattice_desc* d, lattice_t** out) {
   L->sites = L->d.nx * L->d.ny;
   L->nplanes = L->d.dim == 1 ? L->d.nv : (int64_t)L->d.nv * L->d.nv;
   L->cells = L->sites * L->nplanes;
+  L->pitch = plane_pitch_of(L->d);
+  L->span = (L->nplanes - 1) * L->pitch + L->sites;
   L->elem = L->d.dtype == LATTICE_F64 ? 8 : 4;
   L->stream = (hipStream_t)L->d.stream;
-  hipError_t e = hipMalloc(&L->scratch, (size_t)L->cells * L->elem);
+  hipError_t e = hipMalloc(&L->scratch, (size_t)L->span * L->elem);
   if (e != hipSuccess) {
     delete L;
     return e == hipErrorOutOfMemory ? LATTICE_ENOMEM : LATTICE_EHIP;
@@ -166,29 +199,40 @@ int lattice_init(const lattice_desc* d, lattice_t** out) {
   return LATTICE_OK;
 }
 
-// One call of nsteps steps; stream == false leaves out the streaming (every
-// pass has shift 0) and the learned correction: the collision part alone.
-static int advance(lattice_t* L, void* f, const void* u, int64_t n_u_slices,
-                   double tau_p, double kappa, double dt, int64_t nsteps,
-                   bool stream) {
-  if (!L) return LATTICE_EINVAL;
-  L->msg[0] = 0;
-  const lattice_desc& d = L->d;
-  if (!f || !u) return set_err(L, LATTICE_EINVAL, "f or u is NULL");
-  if (((uintptr_t)f % L->elem) || ((uintptr_t)u % L->elem))
-    return set_err(L, LATTICE_EINVAL, "misaligned f or u");
+// Host-side checks and derived parameters of one call of nsteps steps
+// (shared by the handle's entry points and the no-allocation step).
+struct CallPlan {
+  lat::StepArgs a;         // per-pass arguments (fin/fout/u/shift set later)
+  int64_t slice_len = 0;   // elements of one u slice
+  int64_t used = 0;        // u slices the device check reads
+  double umax_ok = 0.0;    // |u| bound of Eq. 3 for this call
+  int64_t passes_per_step = 1;
+  int64_t passes = 0;
+};
+
+static int plan_call(const lattice_desc& d, int64_t sites, size_t elem,
+                     void* f, const void* u, int64_t n_u_slices, double tau_p,
+                     double kappa, double dt, int64_t nsteps, CallPlan* p,
+                     char* msg, size_t msglen) {
+  auto fail = [&](int code, const char* fmt, auto... args) {
+    if (msg) snprintf(msg, msglen, fmt, args...);
+    return code;
+  };
+  if (!f || !u) return fail(LATTICE_EINVAL, "%s", "f or u is NULL");
+  if (((uintptr_t)f % elem) || ((uintptr_t)u % elem))
+    return fail(LATTICE_EINVAL, "%s", "misaligned f or u");
   if (!(dt > 0.0) || !isfinite(dt))
-    return set_err(L, LATTICE_EINVAL, "dt must be > 0");
-  if (!(tau_p > 0.0)) return set_err(L, LATTICE_EINVAL, "tau_p must be > 0");
+    return fail(LATTICE_EINVAL, "%s", "dt must be > 0");
+  if (!(tau_p > 0.0)) return fail(LATTICE_EINVAL, "%s", "tau_p must be > 0");
   if (!(kappa >= 0.0) || !isfinite(kappa))
-    return set_err(L, LATTICE_EINVAL, "kappa must be >= 0");
-  if (nsteps < 0) return set_err(L, LATTICE_EINVAL, "nsteps < 0");
+    return fail(LATTICE_EINVAL, "%s", "kappa must be >= 0");
+  if (nsteps < 0) return fail(LATTICE_EINVAL, "%s", "nsteps < 0");
   const int64_t need =
       d.u_hold > 0 ? (nsteps + d.u_hold - 1) / d.u_hold : 1;
   if (n_u_slices < need || n_u_slices < 1)
-    return set_err(L, LATTICE_EINVAL, "u holds %lld slices, call needs %lld",
-                   (long long)n_u_slices, (long long)need);
-  if (nsteps == 0) return LATTICE_OK;
+    return fail(LATTICE_EINVAL, "u holds %lld slices, call needs %lld",
+                (long long)n_u_slices, (long long)need);
+  if (nsteps == 0) return LATTICE_OK;  // a no-op; nothing else is checked
 
   const double dv = (double)d.vstride * d.dx / dt;
   const int h = (d.nv - 1) / 2;
@@ -196,70 +240,112 @@ static int advance(lattice_t* L, void* f, const void* u, int64_t n_u_slices,
   const double dts = dt / d.nsub;
   const double Dn = kappa * dts / (dv * dv);
   if (!(Dn < 0.5))
-    return set_err(L, LATTICE_EDIFF, "kappa dt_s/dv^2 = %g >= 1/2", Dn);
+    return fail(LATTICE_EDIFF, "kappa dt_s/dv^2 = %g >= 1/2", Dn);
   const bool drag = isfinite(tau_p);
   const double bound = cfl_bound(d.scheme);
-  double umax_ok = 0.0;
   if (drag) {
     // (dt_s/dv)(|u| + Vmax)/tau_p within bound  <=>  |u| within umax_ok
-    umax_ok = bound * tau_p * dv / dts - vmax;
+    p->umax_ok = bound * tau_p * dv / dts - vmax;
     const double cfl0 = (dts / dv) * vmax / tau_p;
-    if (umax_ok < 0.0 || (d.scheme == LATTICE_UPWIND && !(cfl0 < 1.0)))
-      return set_err(L, LATTICE_ECFL, "Vmax alone gives CFL %g", cfl0);
+    if (p->umax_ok < 0.0 || (d.scheme == LATTICE_UPWIND && !(cfl0 < 1.0)))
+      return fail(LATTICE_ECFL, "Vmax alone gives CFL %g", cfl0);
   }
-
-  const int64_t slice_len = (int64_t)d.dim * L->sites;
-  const int64_t used = drag ? need : 0;
-  if (used > 0)
-    HIPCHK(L, lat::launch_cfl_check(u, used * slice_len, umax_ok,
-                                    d.scheme == LATTICE_UPWIND ? 1 : 0,
-                                    d.dtype == LATTICE_F64, L->flag,
-                                    L->stream));
-
-  // passes: per step, 1D does everything in one pass (nsub inline); 2D does
-  // one streaming pass plus (nsub - 1) collision-only passes.
-  const int64_t passes_per_step = d.dim == 1 ? 1 : d.nsub;
-  const int64_t passes = nsteps * passes_per_step;
-  void* bufs[2];
-  if (passes % 2 == 0) {
-    bufs[0] = f;
-    bufs[1] = L->scratch;
-  } else {
-    HIPCHK(L, lat::launch_copy(L->scratch, f, L->cells * (int64_t)L->elem,
-                               L->stream));
-    bufs[0] = L->scratch;
-    bufs[1] = f;
-  }
-
-  lat::StepArgs a;
-  a.flag = L->flag;
+  p->slice_len = (int64_t)d.dim * sites;
+  p->used = drag ? need : 0;
+  // per step, 1D does everything in one pass (nsub inline); 2D does one
+  // streaming pass plus (nsub - 1) collision-only passes.
+  p->passes_per_step = d.dim == 1 ? 1 : d.nsub;
+  p->passes = nsteps * p->passes_per_step;
+  lat::StepArgs& a = p->a;
   a.nx = d.nx;
   a.ny = d.ny;
+  a.pitch = plane_pitch_of(d);
   a.nv = d.nv;
   a.alpha_scale = drag ? dts / (dv * tau_p) : 0.0;
   a.beta = drag ? dts / tau_p : 0.0;
   a.D = Dn;
   a.koren = d.scheme == LATTICE_KOREN;
   a.f64 = d.dtype == LATTICE_F64;
+  a.nsub_inline = d.dim == 1 ? d.nsub : 1;
+  return LATTICE_OK;
+}
+
+// The launch sequence of one call: the device CFL check of the u slices the
+// call reads, the passes ping-ponging between f and twin (with one copy of
+// f into twin first when the number of passes is odd, so that the result
+// lands in f), and after every streaming step the learned correction when L
+// has one attached.  L (optional) supplies profiling and the correction.
+static int run_call(const lattice_desc& d, CallPlan& p, void* f,
+                    const void* u, int64_t nsteps, void* twin, int* flag,
+                    int64_t state_bytes, size_t elem, hipStream_t st,
+                    bool stream, lattice_t* L, double tau_p, double dt,
+                    const char** where, hipError_t* herr) {
+  auto chk = [&](hipError_t e, const char* w) {
+    if (e != hipSuccess) {
+      *where = w;
+      *herr = e;
+      return false;
+    }
+    return true;
+  };
+  if (p.used > 0 &&
+      !chk(lat::launch_cfl_check(u, p.used * p.slice_len, p.umax_ok,
+                                 d.scheme == LATTICE_UPWIND ? 1 : 0,
+                                 d.dtype == LATTICE_F64, flag, st),
+           "cfl check launch"))
+    return LATTICE_EHIP;
+  void* bufs[2];
+  if (p.passes % 2 == 0) {
+    bufs[0] = f;
+    bufs[1] = twin;
+  } else {
+    if (!chk(lat::launch_copy(twin, f, state_bytes, st), "state copy"))
+      return LATTICE_EHIP;
+    bufs[0] = twin;
+    bufs[1] = f;
+  }
+  lat::StepArgs& a = p.a;
+  a.flag = flag;
   int64_t k = 0;
   for (int64_t s = 0; s < nsteps; ++s) {
     const int64_t sl = d.u_hold > 0 ? s / d.u_hold : 0;
-    a.u = (const char*)u + (size_t)(sl * slice_len) * L->elem;
-    for (int64_t ps = 0; ps < passes_per_step; ++ps, ++k) {
+    a.u = (const char*)u + (size_t)(sl * p.slice_len) * elem;
+    for (int64_t ps = 0; ps < p.passes_per_step; ++ps, ++k) {
       a.fin = bufs[k & 1];
       a.fout = bufs[(k + 1) & 1];
       a.shift = (ps == 0 && stream) ? d.vstride : 0;
-      a.nsub_inline = d.dim == 1 ? d.nsub : 1;
-      HIPCHK(L, record_pair(L, false));
-      hipError_t e = d.dim == 1 ? lat::launch_step1d(a, L->stream)
-                                : lat::launch_step2d(a, L->stream);
-      if (e != hipSuccess) return hip_err(L, e, "step kernel launch");
-      HIPCHK(L, record_pair(L, true));
+      if (L && !chk(record_pair(L, false), "event record")) return LATTICE_EHIP;
+      hipError_t e = d.dim == 1 ? lat::launch_step1d(a, st)
+                                : lat::launch_step2d(a, st);
+      if (!chk(e, "step kernel launch")) return LATTICE_EHIP;
+      if (L && !chk(record_pair(L, true), "event record")) return LATTICE_EHIP;
     }
-    if (L->mlp && stream)  // learned face-flux correction (coarse lattice)
-      HIPCHK(L, lat::apply_mlp(L, bufs[k & 1], a.u, dt, tau_p));
+    if (L && L->mlp && stream &&  // learned face-flux correction (coarse)
+        !chk(lat::apply_mlp(L, bufs[k & 1], a.u, dt, tau_p),
+             "correction launch"))
+      return LATTICE_EHIP;
   }
   return LATTICE_OK;
+}
+
+// One call of nsteps steps; stream == false leaves out the streaming (every
+// pass has shift 0) and the learned correction: the collision part alone.
+static int advance(lattice_t* L, void* f, const void* u, int64_t n_u_slices,
+                   double tau_p, double kappa, double dt, int64_t nsteps,
+                   bool stream) {
+  if (!L) return LATTICE_EINVAL;
+  L->msg[0] = 0;
+  CallPlan p;
+  int rc = plan_call(L->d, L->sites, L->elem, f, u, n_u_slices, tau_p, kappa,
+                     dt, nsteps, &p, L->msg, sizeof(L->msg));
+  if (rc != LATTICE_OK || nsteps == 0) return rc;
+  const char* where = "";
+  hipError_t e = hipSuccess;
+  rc = run_call(L->d, p, f, u, nsteps, L->scratch, L->flag,
+                L->span * (int64_t)L->elem, L->elem, L->stream, stream, L,
+                tau_p, dt, &where, &e);
+  if (rc == LATTICE_EHIP) return hip_err(L, e, where);
+  return rc;
 }
 
 int lattice_step(lattice_t* L, void* f, const void* u, int64_t n_u_slices,
@@ -272,22 +358,25 @@ int lattice_collide(lattice_t* L, void* f, const void* u, int64_t n_u_slices,
   return advance(L, f, u, n_u_slices, tau_p, kappa, dt, nsteps, false);
 }
 
+// Report a set sticky flag (whose value the host has already read) and
+// queue its clearing: stream order makes every later call see it cleared.
+static int report_flag(lattice_t* L, int h) {
+  if (!h) return LATTICE_OK;
+  hipError_t e = lat::launch_clear_flag(L->flag, L->stream);
+  if (e != hipSuccess) return hip_err(L, e, "flag clear");
+  return set_err(L, LATTICE_ECFL,
+                 "drift CFL bound (Eq. 3) violated or non-finite u");
+}
+
+// Wait for the stream and read the flag: one copy into pinned memory.
 static int read_flag(lattice_t* L) {
-  int h = 0;
-  hipError_t e = hipMemcpyAsync(&h, L->flag, sizeof(int),
+  int* h = (int*)(L->host_red + 7);
+  hipError_t e = hipMemcpyAsync(h, L->flag, sizeof(int),
                                 hipMemcpyDeviceToHost, L->stream);
   if (e != hipSuccess) return hip_err(L, e, "flag copy");
   e = hipStreamSynchronize(L->stream);
   if (e != hipSuccess) return hip_err(L, e, "stream sync");
-  if (h) {
-    e = lat::launch_clear_flag(L->flag, L->stream);
-    if (e != hipSuccess) return hip_err(L, e, "flag clear");
-    e = hipStreamSynchronize(L->stream);
-    if (e != hipSuccess) return hip_err(L, e, "stream sync");
-    return set_err(L, LATTICE_ECFL,
-                   "drift CFL bound (Eq. 3) violated or non-finite u");
-  }
-  return LATTICE_OK;
+  return report_flag(L, *h);
 }
 
 int lattice_moments(lattice_t* L, const void* f, double dt,
@@ -299,10 +388,12 @@ int lattice_moments(lattice_t* L, const void* f, double dt,
   const lattice_desc& d = L->d;
   const double dv = (double)d.vstride * d.dx / dt;
   const double w = d.dim == 1 ? d.dx * dv : d.dx * d.dx * dv * dv;
-  HIPCHK(L, lat::launch_moments(f, L->sites, d.nv, d.dim,
+  // the moments and the sticky flag come back in one copy (red[6] holds
+  // the flag) with one wait
+  HIPCHK(L, lat::launch_moments(f, L->sites, L->pitch, d.nv, d.dim,
                                 d.dtype == LATTICE_F64, w, dv, L->plane_sums,
-                                L->red, L->stream));
-  HIPCHK(L, hipMemcpyAsync(L->host_red, L->red, sizeof(double) * 6,
+                                L->flag, L->red, L->stream));
+  HIPCHK(L, hipMemcpyAsync(L->host_red, L->red, sizeof(double) * 7,
                            hipMemcpyDeviceToHost, L->stream));
   HIPCHK(L, hipStreamSynchronize(L->stream));
   const double* r = L->host_red;
@@ -318,7 +409,7 @@ int lattice_moments(lattice_t* L, const void* f, double dt,
   int nonfinite = 0;
   for (int i = 0; i < 6; ++i) nonfinite |= !isfinite(r[i]);
   out->nonfinite = nonfinite;
-  int rc = read_flag(L);
+  int rc = report_flag(L, r[6] != 0.0);
   if (rc != LATTICE_OK) return rc;
   if (nonfinite)
     return set_err(L, LATTICE_ENONFINITE, "moments are not finite");
@@ -333,7 +424,7 @@ int lattice_density(lattice_t* L, const void* f, double dt, double* rho) {
   const lattice_desc& d = L->d;
   const double dv = (double)d.vstride * d.dx / dt;
   const double dvd = d.dim == 1 ? dv : dv * dv;
-  HIPCHK(L, lat::launch_density(f, L->sites, (int)L->nplanes,
+  HIPCHK(L, lat::launch_density(f, L->sites, L->pitch, (int)L->nplanes,
                                 d.dtype == LATTICE_F64, dvd, rho, L->stream));
   return LATTICE_OK;
 }
@@ -397,7 +488,7 @@ int lattice_stability(lattice_t* L, const void* u, int64_t n_u_slices,
 int lattice_copy_state(lattice_t* L, void* dst, const void* src) {
   if (!L) return LATTICE_EINVAL;
   if (!dst || !src) return set_err(L, LATTICE_EINVAL, "NULL pointer");
-  HIPCHK(L, lat::launch_copy(dst, src, L->cells * (int64_t)L->elem,
+  HIPCHK(L, lat::launch_copy(dst, src, L->span * (int64_t)L->elem,
                              L->stream));
   return LATTICE_OK;
 }

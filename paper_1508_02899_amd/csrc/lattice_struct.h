@@ -12,6 +12,9 @@ struct lattice {
   int64_t sites;    // nx * ny
   int64_t nplanes;  // nv^dim
   int64_t cells;    // sites * nplanes
+  int64_t pitch;    // elements from one velocity plane to the next (>= sites)
+  int64_t span;     // elements from the first to the last state element
+                    // + 1: (nplanes - 1) * pitch + sites
   size_t elem;      // sizeof state element
   hipStream_t stream;
   void* scratch = nullptr;      // state-sized ping-pong twin

@@ -76,9 +76,9 @@ __device__ void block_sum2(double& a, double& b, double* sa, double* sb) {
 // periodic.  partial[(k * 2 + axis) * nblocks + block][2].
 template <typename T>
 __global__ __launch_bounds__(kS1Block) void k_s1_corr(
-    const T* __restrict__ f, const T* __restrict__ h, int64_t nx, int64_t ny,
-    int nplanes, const int32_t* __restrict__ rs, int naxes,
-    double* __restrict__ partial) {
+    const T* __restrict__ f, int64_t fpitch, const T* __restrict__ h,
+    int64_t nx, int64_t ny, int nplanes, const int32_t* __restrict__ rs,
+    int naxes, double* __restrict__ partial) {
   __shared__ double sa[kS1Block], sb[kS1Block];
   const int64_t sites = nx * ny;
   const int64_t i = (int64_t)blockIdx.x * kS1Block + threadIdx.x;
@@ -97,10 +97,10 @@ __global__ __launch_bounds__(kS1Block) void k_s1_corr(
     }
     double ra = 0.0, rb = 0.0;
     for (int J = 0; J < nplanes; ++J) {
-      const double a = (double)f[(size_t)J * sites + i];
+      const double a = (double)f[(size_t)J * fpitch + i];
       num += a * (double)h[(size_t)J * sites + j];
       ra += a;
-      rb += (double)f[(size_t)J * sites + j];
+      rb += (double)f[(size_t)J * fpitch + j];
     }
     den = ra * rb;
   }
@@ -186,7 +186,8 @@ extern "C" int lattice_s1(lattice_t* L, const void* f, double dt, int32_t nr,
       hipLaunchKernelGGL(lat::k_s1_dist<float>, dim3(gd), dim3(lat::kS1Block),
                          0, st, d.nv, (float*)D);
     e = hipGetLastError();
-    // column-major view: F (sites x np, ld sites), D (np x np), h = F D
+    // column-major view: F (sites x np, ld = the plane pitch), D (np x np),
+    // h = F D (sites x np, ld sites)
     if (e == hipSuccess &&
         (rocblas_create_handle(&handle) != rocblas_status_success ||
          rocblas_set_stream(handle, st) != rocblas_status_success))
@@ -198,7 +199,7 @@ extern "C" int lattice_s1(lattice_t* L, const void* f, double dt, int32_t nr,
         bs = rocblas_dgemm(handle, rocblas_operation_none,
                            rocblas_operation_none, (rocblas_int)sites,
                            (rocblas_int)np, (rocblas_int)np, &one,
-                           (const double*)f, (rocblas_int)sites,
+                           (const double*)f, (rocblas_int)L->pitch,
                            (const double*)D, (rocblas_int)np, &zero,
                            (double*)h, (rocblas_int)sites);
       } else {
@@ -206,7 +207,7 @@ extern "C" int lattice_s1(lattice_t* L, const void* f, double dt, int32_t nr,
         bs = rocblas_sgemm(handle, rocblas_operation_none,
                            rocblas_operation_none, (rocblas_int)sites,
                            (rocblas_int)np, (rocblas_int)np, &one,
-                           (const float*)f, (rocblas_int)sites,
+                           (const float*)f, (rocblas_int)L->pitch,
                            (const float*)D, (rocblas_int)np, &zero,
                            (float*)h, (rocblas_int)sites);
       }
@@ -218,12 +219,14 @@ extern "C" int lattice_s1(lattice_t* L, const void* f, double dt, int32_t nr,
     const dim3 g((unsigned)nb, (unsigned)(nr * naxes));
     if (f64)
       hipLaunchKernelGGL(lat::k_s1_corr<double>, g, dim3(lat::kS1Block), 0, st,
-                         (const double*)f, (const double*)h, (int64_t)d.nx,
+                         (const double*)f, L->pitch, (const double*)h,
+                         (int64_t)d.nx,
                          (int64_t)(d.dim == 2 ? d.ny : 1), (int)np, dr, naxes,
                          partial);
     else
       hipLaunchKernelGGL(lat::k_s1_corr<float>, g, dim3(lat::kS1Block), 0, st,
-                         (const float*)f, (const float*)h, (int64_t)d.nx,
+                         (const float*)f, L->pitch, (const float*)h,
+                         (int64_t)d.nx,
                          (int64_t)(d.dim == 2 ? d.ny : 1), (int)np, dr, naxes,
                          partial);
     hipLaunchKernelGGL(lat::k_s1_final, dim3((unsigned)(nr * naxes)),

@@ -24,7 +24,8 @@ OK, EINVAL, ECFL, EDIFF, EHIP, ENOMEM, ENONFINITE, ENOTSUP = (
 
 # every symbol declared in include/lattice.h
 EXPORTS = (
-    "lattice_desc_default", "lattice_velocity", "lattice_init", "lattice_step",
+    "lattice_desc_default", "lattice_plane_pitch", "lattice_velocity",
+    "lattice_init", "lattice_step",
     "lattice_collide",
     "lattice_moments", "lattice_density", "lattice_stability",
     "lattice_copy_state", "lattice_sync", "lattice_profile", "lattice_rho_r2",
@@ -66,6 +67,7 @@ class Desc(ctypes.Structure):
         ("nsub", ctypes.c_int32),
         ("u_hold", ctypes.c_int64),
         ("stream", ctypes.c_void_p),
+        ("plane_pitch", ctypes.c_int64),
     ]
 
 
@@ -109,6 +111,7 @@ def load_library(path: str = LIB_PATH):
                          ctypes.c_int)
     pdesc = ctypes.POINTER(Desc)
     L.lattice_desc_default.argtypes = [pdesc]
+    L.lattice_plane_pitch.argtypes = [pdesc, ctypes.POINTER(i64)]
     L.lattice_velocity.argtypes = [pdesc, dbl, ctypes.POINTER(dbl),
                                    ctypes.POINTER(dbl)]
     L.lattice_init.argtypes = [pdesc, ctypes.POINTER(vp)]
@@ -183,6 +186,49 @@ class LatticeSpec:
     dtype: str = "f32"
     nsub: int = 1
     u_hold: int = 0
+    plane_pitch: int = 0   # elements between velocity planes; 0 = nx*ny
+
+    @property
+    def sites(self) -> int:
+        return self.nx * (self.ny if self.dim == 2 else 1)
+
+    @property
+    def pitch(self) -> int:
+        """Elements from one velocity plane of the state to the next."""
+        return self.plane_pitch or self.sites
+
+    @property
+    def state_strides(self):
+        """Element strides of a state tensor of shape state_shape."""
+        if self.dim == 1:
+            return (self.pitch, 1)
+        return (self.pitch, self.nx, 1)
+
+    @property
+    def state_span(self) -> int:
+        """Elements from the first to the last element of a state, + 1."""
+        return (self.nplanes - 1) * self.pitch + self.sites
+
+    def empty_state(self, device="cuda", dtype=None):
+        """An uninitialised state tensor in this spec's layout (a strided
+        view of one buffer when the plane pitch pads the planes)."""
+        torch = _torch()
+        if dtype is None:
+            dtype = torch.float64 if self.dtype == "f64" else torch.float32
+        buf = torch.empty(self.nplanes * self.pitch, dtype=dtype,
+                          device=device)
+        return buf.as_strided(self.state_shape, self.state_strides)
+
+    def state_from(self, values, device="cuda"):
+        """A state tensor in this spec's layout holding values (array-like
+        of shape state_shape)."""
+        import numpy as np
+        torch = _torch()
+        t = self.empty_state(device)
+        src = values if isinstance(values, torch.Tensor) else \
+            torch.from_numpy(np.ascontiguousarray(values))
+        t.copy_(src)
+        return t
 
     def velocity(self, dt: float):
         """(dv, Vmax) for time step dt: dv = vstride dx / dt, Vmax = h dv."""
@@ -238,6 +284,36 @@ def require_tensor(t, name, dtype, shape=None, numel=None, min_numel=None,
     return ctypes.c_void_p(t.data_ptr())
 
 
+def require_state(t, spec, name, dtype, cuda=True):
+    """Raise unless t is a state tensor of spec: dtype, shape state_shape,
+    element strides state_strides (plain contiguity when the planes are not
+    padded) and a buffer that holds the whole span; then the device."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} dtype {t.dtype} != {dtype}")
+    if tuple(t.shape) != tuple(spec.state_shape):
+        raise ValueError(f"{name} shape {tuple(t.shape)} != "
+                         f"{tuple(spec.state_shape)}")
+    if spec.pitch == spec.sites:
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+    else:
+        if tuple(t.stride()) != tuple(spec.state_strides):
+            raise ValueError(f"{name} strides {tuple(t.stride())} != "
+                             f"{tuple(spec.state_strides)} (plane pitch "
+                             f"{spec.pitch})")
+        have = t.untyped_storage().nbytes() // t.element_size() - \
+            t.storage_offset()
+        if have < spec.state_span:
+            raise ValueError(f"{name} buffer holds {have} elements, the "
+                             f"padded state spans {spec.state_span}")
+    if cuda and not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
 def require_cuda(**tensors):
     """Raise unless every named tensor lives on the GPU (checked after the
     sizes of all of them, so that a size error is reported first)."""
@@ -263,14 +339,7 @@ class Lattice:
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
-        d = Desc()
-        self.lib.lattice_desc_default(ctypes.byref(d))
-        d.dim, d.nx, d.ny, d.nv = spec.dim, spec.nx, spec.ny, spec.nv
-        d.vstride, d.dx = spec.vstride, spec.dx
-        d.scheme = SCHEMES[spec.scheme]
-        d.dtype = F64 if spec.dtype == "f64" else F32
-        d.nsub, d.u_hold = spec.nsub, spec.u_hold
-        d.stream = ctypes.c_void_p(stream.cuda_stream)
+        d = _desc(spec, stream)
         h = ctypes.c_void_p()
         self._check(self.lib.lattice_init(ctypes.byref(d), ctypes.byref(h)))
         self._L = h
@@ -291,6 +360,9 @@ class Lattice:
         return require_tensor(t, name, self.torch_dtype, shape=shape,
                               cuda=cuda)
 
+    def _state_ptr(self, t, name="f", cuda=True):
+        return require_state(t, self.spec, name, self.torch_dtype, cuda=cuda)
+
     # -- API -------------------------------------------------------------
     def step(self, f, u, tau_p: float, kappa: float, dt: float, nsteps: int,
              check: bool = True):
@@ -310,7 +382,7 @@ class Lattice:
 
     def _advance(self, fn, f, u, tau_p, kappa, dt, nsteps, check):
         s = self.spec
-        fp = self._tensor_ptr(f, s.state_shape, "f", cuda=False)
+        fp = self._state_ptr(f, "f", cuda=False)
         per = s.dim * s.nx * (s.ny if s.dim == 2 else 1)
         up = self._tensor_ptr(u, None, "u", cuda=False)
         if u.numel() % per or u.numel() == 0:
@@ -324,7 +396,7 @@ class Lattice:
 
     def moments(self, f, dt: float) -> dict:
         """FP64 mass / momentum / second moment / variance (synchronous)."""
-        fp = self._tensor_ptr(f, self.spec.state_shape, "f")
+        fp = self._state_ptr(f, "f")
         m = Moments()
         rc = self.lib.lattice_moments(self._L, fp, float(dt), ctypes.byref(m))
         out = {
@@ -343,7 +415,7 @@ class Lattice:
         """rho(x) = dv^dim sum_j f as a new FP64 CUDA tensor [ny, nx]."""
         torch = _torch()
         s = self.spec
-        fp = self._tensor_ptr(f, s.state_shape, "f")
+        fp = self._state_ptr(f, "f")
         rho = torch.empty((s.ny if s.dim == 2 else 1, s.nx),
                           dtype=torch.float64, device=f.device)
         self._check(self.lib.lattice_density(self._L, fp, float(dt),
@@ -384,7 +456,7 @@ class Lattice:
         rr = np.ascontiguousarray(np.asarray(r, dtype=np.int32))
         out = np.empty(rr.size, dtype=np.float64)
         self._check(self.lib.lattice_s1(
-            self._L, self._tensor_ptr(f, self.spec.state_shape, "f"),
+            self._L, self._state_ptr(f, "f"),
             float(dt), int(rr.size),
             rr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
             out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
@@ -417,8 +489,8 @@ class Lattice:
         return out[0], out[1]
 
     def copy_state(self, dst, src):
-        dp = self._tensor_ptr(dst, self.spec.state_shape, "dst", cuda=False)
-        sp = self._tensor_ptr(src, self.spec.state_shape, "src", cuda=False)
+        dp = self._state_ptr(dst, "dst", cuda=False)
+        sp = self._state_ptr(src, "src", cuda=False)
         require_cuda(dst=dst, src=src)
         self._check(self.lib.lattice_copy_state(self._L, dp, sp))
 
@@ -785,6 +857,34 @@ def strerror(code: int) -> str:
     return load_library().lattice_strerror(code).decode()
 
 
+def _desc(spec: LatticeSpec, stream=None) -> Desc:
+    """The C descriptor of a LatticeSpec."""
+    L = load_library()
+    d = Desc()
+    L.lattice_desc_default(ctypes.byref(d))
+    d.dim, d.nx, d.ny, d.nv = spec.dim, spec.nx, spec.ny, spec.nv
+    d.vstride, d.dx = spec.vstride, spec.dx
+    d.scheme = SCHEMES[spec.scheme]
+    d.dtype = F64 if spec.dtype == "f64" else F32
+    d.nsub, d.u_hold = spec.nsub, spec.u_hold
+    d.plane_pitch = spec.plane_pitch
+    if stream is not None:
+        d.stream = ctypes.c_void_p(stream.cuda_stream)
+    return d
+
+
+def recommended_pitch(spec: LatticeSpec) -> int:
+    """The plane pitch the library recommends for this lattice
+    (lattice_plane_pitch): nx*ny, or padded when a plane spans a multiple
+    of 64 KiB."""
+    p = ctypes.c_int64()
+    rc = load_library().lattice_plane_pitch(ctypes.byref(_desc(spec)),
+                                            ctypes.byref(p))
+    if rc != OK:
+        raise LatticeError(rc, strerror(rc))
+    return p.value
+
+
 def velocity(spec: LatticeSpec, dt: float):
     """(dv, Vmax) computed by the library (host-only call)."""
     L = load_library()
@@ -801,6 +901,7 @@ def velocity(spec: LatticeSpec, dt: float):
 
 
 __all__ = ["Lattice", "LatticeSpec", "LatticeError", "LatticeLibraryMissing",
-           "require_tensor", "require_cuda",
+           "require_tensor", "require_cuda", "require_state",
+           "recommended_pitch",
            "Batch", "Member", "Mlp", "restrict", "load_library", "strerror",
            "velocity", "EXPORTS", "MLP_NPARAMS"]

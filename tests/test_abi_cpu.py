@@ -100,3 +100,43 @@ def test_missing_library_fails_loudly(tmp_path):
             lattice.load_library(str(tmp_path / "nope.so"))
     finally:
         lattice._lib = saved
+
+
+def test_plane_pitch_recommendation_and_validation(lib):
+    """lattice_plane_pitch pads the planes of 2D states whose plane spans a
+    multiple of 64 KiB by 64 elements, and leaves other lattices
+    contiguous; descriptors with a pitch below nx*ny (or, in 1D, other than
+    nx) are refused."""
+    from paper_1508_02899_amd.lattice import Desc, EINVAL, F64
+    d = Desc()
+    lib.lattice_desc_default(ctypes.byref(d))
+    p = ctypes.c_int64()
+
+    def rec(dim, nx, ny, nv, dtype=0):
+        d.dim, d.nx, d.ny, d.nv, d.dtype = dim, nx, ny, nv, dtype
+        assert lib.lattice_plane_pitch(ctypes.byref(d), ctypes.byref(p)) == 0
+        return p.value
+
+    assert rec(2, 512, 512, 33) == 512 * 512 + 64
+    assert rec(2, 256, 256, 65) == 256 * 256 + 64
+    assert rec(2, 128, 128, 17) == 128 * 128 + 64       # 64 KiB planes
+    assert rec(2, 128, 64, 17) == 128 * 64               # 32 KiB planes
+    assert rec(2, 128, 64, 17, F64) == 128 * 64 + 64     # 64 KiB in FP64
+    assert rec(2, 70, 9, 17) == 630
+    assert rec(1, 16384, 1, 129) == 16384
+    dv, vm = ctypes.c_double(), ctypes.c_double()
+    d.dim, d.nx, d.ny, d.nv, d.dtype = 2, 70, 9, 17, 0
+    for pitch, ok in [(0, True), (630, True), (700, True), (629, False),
+                      (-1, False)]:
+        d.plane_pitch = pitch
+        rc = lib.lattice_velocity(ctypes.byref(d), 0.1, ctypes.byref(dv),
+                                  ctypes.byref(vm))
+        assert (rc == 0) == ok, pitch
+    d.dim, d.nx, d.ny = 1, 300, 1
+    for pitch, ok in [(0, True), (300, True), (301, False)]:
+        d.plane_pitch = pitch
+        rc = lib.lattice_velocity(ctypes.byref(d), 0.1, ctypes.byref(dv),
+                                  ctypes.byref(vm))
+        assert (rc == 0) == ok, pitch
+    d.plane_pitch = 0
+    assert lib.lattice_plane_pitch(None, ctypes.byref(p)) == EINVAL

@@ -138,3 +138,34 @@ def test_restrict_checks_its_input():
         B.restrict(torch.zeros(65, 4, dtype=torch.float64), 1)
     with pytest.raises(ValueError, match="dim"):
         B.restrict(torch.zeros(65, 4), 3)
+
+
+def test_padded_state_views_are_checked():
+    """A state with padded velocity planes is a strided view of one buffer;
+    the binding accepts exactly that view and refuses plain contiguous
+    tensors, other strides and other shapes."""
+    spec = B.LatticeSpec(dim=2, nx=8, ny=4, nv=5, dx=0.1, plane_pitch=40)
+    assert spec.state_strides == (40, 8, 1)
+    assert spec.state_span == 24 * 40 + 32
+    good = spec.empty_state(device="cpu")
+    assert tuple(good.stride()) == (40, 8, 1)
+    with pytest.raises(TypeError, match="CUDA"):
+        B.require_state(good, spec, "f", torch.float32)
+    B.require_state(good, spec, "f", torch.float32, cuda=False)
+    with pytest.raises(ValueError, match="strides"):
+        B.require_state(torch.zeros(25, 4, 8), spec, "f", torch.float32)
+    # a view of the right strides but the wrong shape
+    with pytest.raises(ValueError, match="shape"):
+        B.require_state(good[:, :3], spec, "f", torch.float32)
+    with pytest.raises(TypeError, match="dtype"):
+        B.require_state(good.double(), spec, "f", torch.float32)
+    # values survive the round trip through the padded layout
+    import numpy as np
+    a = np.arange(25 * 32, dtype=np.float32).reshape(25, 4, 8)
+    t = spec.state_from(a, device="cpu")
+    assert np.array_equal(t.numpy(), a)
+    # an unpadded spec takes plain contiguous tensors
+    flat = B.LatticeSpec(dim=2, nx=8, ny=4, nv=5, dx=0.1)
+    assert flat.pitch == 32
+    B.require_state(torch.zeros(25, 4, 8), flat, "f", torch.float32,
+                    cuda=False)

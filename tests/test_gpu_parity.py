@@ -310,14 +310,18 @@ def test_host_side_errors():
     lat.close()
 
 
-def test_2d_512x512_v33_full_size_sampled_sites():
-    """2D 512^2 x 33^2 FP32 (1.14 GB state), the bench launch: one step on
-    the GPU; 64 sampled sites (corners, edges, interior) recomputed one by
-    one by the oracle from their streamed velocity columns."""
+@pytest.mark.parametrize("padded", [True, False])
+def test_2d_512x512_v33_full_size_sampled_sites(padded):
+    """2D 512^2 x 33^2 FP32 (1.14 GB state), the bench launch (padded
+    planes at the recommended pitch, as the benchmark runs) and the
+    contiguous layout: one step on the GPU; 64 sampled sites (corners,
+    edges, interior) recomputed one by one by the oracle from their
+    streamed velocity columns."""
     import torch
     import oracle
     from paper_1508_02899_amd import Lattice, LatticeSpec, inputs
-    say("config-3 full size sampled parity")
+    from paper_1508_02899_amd.lattice import recommended_pitch
+    say(f"config-3 full size sampled parity, padded={padded}")
     n, nv, L = 512, 33, 2 * math.pi
     h = (nv - 1) // 2
     u = inputs.flow2d_streamfunction(n, L, 1, seed=inputs.seed_for(3))
@@ -331,8 +335,14 @@ def test_2d_512x512_v33_full_size_sampled_sites():
     rng = np.random.default_rng(16)
     f0 = torch.rand((nv * nv, n, n), generator=torch.Generator().manual_seed(3),
                     dtype=torch.float32)
-    lat = Lattice(LatticeSpec(dim=2, nx=n, ny=n, nv=nv, dx=dx))
-    fd = f0.cuda()
+    spec = LatticeSpec(dim=2, nx=n, ny=n, nv=nv, dx=dx)
+    if padded:
+        spec.plane_pitch = recommended_pitch(spec)
+        assert spec.plane_pitch == n * n + 64
+        fd = spec.state_from(f0)
+    else:
+        fd = f0.cuda()
+    lat = Lattice(spec)
     lat.step(fd, torch.from_numpy(u).cuda(), tau_p, p["kappa"], dt, 1)
     lat.sync()
     out = fd.cpu().numpy()
