@@ -58,7 +58,8 @@ enum {
   LATTICE_EHIP = -4,       /* HIP runtime error; lattice_last_error explains */
   LATTICE_ENOMEM = -5,     /* device allocation failed */
   LATTICE_ENONFINITE = -6, /* moments are NaN or Inf */
-  LATTICE_ENOTSUP = -7     /* valid but not compiled in (2D nv, see below) */
+  LATTICE_ENOTSUP = -7,    /* valid but not compiled in (2D nv, see below) */
+  LATTICE_ETOOBIG = -8     /* state too large for lattice_step_noalloc */
 };
 
 /*
@@ -181,6 +182,34 @@ int lattice_step(lattice_t* L, void* f, const void* u, int64_t n_u_slices,
  */
 int lattice_collide(lattice_t* L, void* f, const void* u, int64_t n_u_slices,
                     double tau_p, double kappa, double dt, int64_t nsteps);
+
+/*
+ * lattice_step without a handle and without any allocation, for callers
+ * that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  *d describes the lattice
+ * as for lattice_init (its stream field selects the stream); f, u,
+ * n_u_slices, tau_p, kappa, dt, nsteps and the host-side checks (EINVAL,
+ * EDIFF, ECFL, ENOTSUP) are those of lattice_step, and the launch sequence
+ * is the same, with the same kernels, so the result is bit-identical.
+ *
+ * Scratch: the state's ping-pong twin and the CFL flag live in one static
+ * device array of LATTICE_NOALLOC_MAX_BYTES (+256) bytes that each GPU the
+ * library runs on holds until the process ends; a state larger than that
+ * returns LATTICE_ETOOBIG.  The first call on a device looks the array's
+ * address up (hipGetSymbolAddress, no allocation); make that first call
+ * outside any graph capture.  Every call on one GPU shares that GPU's
+ * array: calls that overlap on one GPU (on different streams, or from
+ * different threads) race and must not be issued.
+ *
+ * status (device int32, optional): receives, in stream order at the end of
+ * the call, 0 when every step ran, nonzero when the device check of Eq. 3
+ * (or finiteness of u) failed, in which case every step of the call was a
+ * no-op (f keeps its state).  Asynchronous; returns without waiting.
+ */
+#define LATTICE_NOALLOC_MAX_BYTES (64ll << 20)
+int lattice_step_noalloc(const lattice_desc* d, void* f, const void* u,
+                         int64_t n_u_slices, double tau_p, double kappa,
+                         double dt, int64_t nsteps, int32_t* status);
 
 /*
  * FP64 moments of f (device, read-only) for time step dt (which fixes dv),

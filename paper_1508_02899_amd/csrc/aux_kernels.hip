@@ -188,6 +188,10 @@ __global__ void k_copy1(const unsigned char* __restrict__ s,
 
 __global__ void k_clear(int* flag) { *flag = 0; }
 
+__global__ void k_flag_out(const int* flag, int32_t* status) {
+  *status = *flag;
+}
+
 __global__ void k_clear_u64(unsigned long long* p) { *p = 0ull; }
 
 int grid_for(int64_t n) {
@@ -276,6 +280,11 @@ hipError_t launch_copy(void* dst, const void* src, int64_t bytes,
 
 hipError_t launch_clear_flag(int* flag, hipStream_t s) {
   hipLaunchKernelGGL(k_clear, dim3(1), dim3(1), 0, s, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_flag_out(const int* flag, int32_t* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_flag_out, dim3(1), dim3(1), 0, s, flag, status);
   return hipGetLastError();
 }
 

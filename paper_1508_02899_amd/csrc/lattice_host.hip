@@ -8,6 +8,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -358,6 +359,89 @@ int lattice_collide(lattice_t* L, void* f, const void* u, int64_t n_u_slices,
   return advance(L, f, u, n_u_slices, tau_p, kappa, dt, nsteps, false);
 }
 
+}  // extern "C"
+
+// ---- the step entry point that allocates nothing ---------------------------
+namespace {
+
+// Scratch of lattice_step_noalloc on every GPU the library runs on: the
+// sticky flag word at offset 0, the ping-pong twin of the state from offset
+// 256.  In host code the name stands for the host-side shadow, not for the
+// device memory: kernels and copies get the address hipGetSymbolAddress
+// returns for the current device (noalloc_scratch()).
+__device__ __align__(256) unsigned char scratch[LATTICE_NOALLOC_MAX_BYTES +
+                                                256];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+unsigned char* g_noalloc_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch (looked up once per device, with
+// that device current).  nullptr on failure.
+unsigned char* noalloc_scratch(hipError_t* err) {
+  int dev = 0;
+  *err = hipGetDevice(&dev);
+  if (*err != hipSuccess) return nullptr;
+  if (dev < 0 || dev >= kMaxDevices) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* ptr = nullptr;
+    *err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (*err != hipSuccess) return nullptr;
+    g_noalloc_ptr[dev] = (unsigned char*)ptr;
+  }
+  return g_noalloc_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+int lattice_step_noalloc(const lattice_desc* d, void* f, const void* u,
+                         int64_t n_u_slices, double tau_p, double kappa,
+                         double dt, int64_t nsteps, int32_t* status) {
+  if (bad_desc(d)) return LATTICE_EINVAL;
+  lattice_desc dd = *d;
+  if (dd.dim == 1) dd.ny = 1;
+  if (dd.dim == 1 && !lat::step1d_supported(dd.nv, dd.dtype == LATTICE_F64))
+    return LATTICE_ENOTSUP;
+  if (dd.dim == 2 && !lat::step2d_supported(dd.nv, dd.dtype == LATTICE_F64))
+    return LATTICE_ENOTSUP;
+  if (status && ((uintptr_t)status % sizeof(int32_t)))
+    return LATTICE_EINVAL;
+  const int64_t sites = dd.nx * dd.ny;
+  const int64_t nplanes = dd.dim == 1 ? dd.nv : (int64_t)dd.nv * dd.nv;
+  const int64_t span = (nplanes - 1) * plane_pitch_of(dd) + sites;
+  const size_t elem = dd.dtype == LATTICE_F64 ? 8 : 4;
+  if ((uint64_t)span * elem > (uint64_t)LATTICE_NOALLOC_MAX_BYTES)
+    return LATTICE_ETOOBIG;
+  CallPlan p;
+  int rc = plan_call(dd, sites, elem, f, u, n_u_slices, tau_p, kappa, dt,
+                     nsteps, &p, nullptr, 0);
+  if (rc != LATTICE_OK) return rc;
+  hipError_t e = hipSuccess;
+  unsigned char* base = noalloc_scratch(&e);
+  if (!base) return LATTICE_EHIP;
+  int* flag = (int*)base;
+  void* twin = base + 256;
+  const hipStream_t st = (hipStream_t)dd.stream;
+  // the flag starts at zero on every call (the array keeps the last call's
+  // contents); cleared by a kernel so that the call can be captured
+  if (lat::launch_clear_flag(flag, st) != hipSuccess) return LATTICE_EHIP;
+  if (nsteps > 0) {
+    const char* where = "";
+    rc = run_call(dd, p, f, u, nsteps, twin, flag, span * (int64_t)elem,
+                  elem, st, true, nullptr, tau_p, dt, &where, &e);
+    if (rc != LATTICE_OK) return rc;
+  }
+  if (status && lat::launch_flag_out(flag, status, st) != hipSuccess)
+    return LATTICE_EHIP;
+  return LATTICE_OK;
+}
+
 // Report a set sticky flag (whose value the host has already read) and
 // queue its clearing: stream order makes every later call see it cleared.
 static int report_flag(lattice_t* L, int h) {
@@ -543,6 +627,8 @@ const char* lattice_strerror(int code) {
     case LATTICE_ENOMEM: return "out of device memory";
     case LATTICE_ENONFINITE: return "non-finite moments";
     case LATTICE_ENOTSUP: return "no kernel compiled for this lattice";
+    case LATTICE_ETOOBIG:
+      return "state larger than the static scratch of lattice_step_noalloc";
     default: return "unknown error";
   }
 }

@@ -74,5 +74,7 @@ hipError_t launch_density(const void* f, int64_t sites, int64_t pitch,
 hipError_t launch_copy(void* dst, const void* src, int64_t bytes,
                        hipStream_t s);
 hipError_t launch_clear_flag(int* flag, hipStream_t s);
+// *status = *flag (stream-ordered; a kernel, so that it can be captured).
+hipError_t launch_flag_out(const int* flag, int32_t* status, hipStream_t s);
 
 }  // namespace lat

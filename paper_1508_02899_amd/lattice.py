@@ -19,14 +19,15 @@ UPWIND, KOREN = 0, 1
 F32, F64 = 0, 1
 SCHEMES = {"upwind": UPWIND, "koren": KOREN}
 
-OK, EINVAL, ECFL, EDIFF, EHIP, ENOMEM, ENONFINITE, ENOTSUP = (
-    0, -1, -2, -3, -4, -5, -6, -7)
+OK, EINVAL, ECFL, EDIFF, EHIP, ENOMEM, ENONFINITE, ENOTSUP, ETOOBIG = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8)
+NOALLOC_MAX_BYTES = 64 << 20  # LATTICE_NOALLOC_MAX_BYTES
 
 # every symbol declared in include/lattice.h
 EXPORTS = (
     "lattice_desc_default", "lattice_plane_pitch", "lattice_velocity",
     "lattice_init", "lattice_step",
-    "lattice_collide",
+    "lattice_collide", "lattice_step_noalloc",
     "lattice_moments", "lattice_density", "lattice_stability",
     "lattice_copy_state", "lattice_sync", "lattice_profile", "lattice_rho_r2",
     "lattice_flow1d_modes", "lattice_flow2d_modes", "lattice_s1",
@@ -117,6 +118,8 @@ def load_library(path: str = LIB_PATH):
     L.lattice_init.argtypes = [pdesc, ctypes.POINTER(vp)]
     L.lattice_step.argtypes = [vp, vp, vp, i64, dbl, dbl, dbl, i64]
     L.lattice_collide.argtypes = [vp, vp, vp, i64, dbl, dbl, dbl, i64]
+    L.lattice_step_noalloc.argtypes = [pdesc, vp, vp, i64, dbl, dbl, dbl,
+                                       i64, vp]
     L.lattice_moments.argtypes = [vp, vp, dbl, ctypes.POINTER(Moments)]
     L.lattice_density.argtypes = [vp, vp, dbl, vp]
     L.lattice_stability.argtypes = [vp, vp, i64, dbl, dbl, dbl,
@@ -885,6 +888,38 @@ def recommended_pitch(spec: LatticeSpec) -> int:
     return p.value
 
 
+def step_noalloc(spec: LatticeSpec, f, u, tau_p: float, kappa: float,
+                 dt: float, nsteps: int, status=None, stream=None) -> int:
+    """lattice_step_noalloc: advance f in place without a handle and without
+    any device allocation (the library's static scratch holds the state's
+    twin; states up to NOALLOC_MAX_BYTES).  status: optional int32 CUDA
+    tensor of one element that receives 0 (all steps ran) or nonzero (the
+    CFL check failed; the call's steps were no-ops).  Asynchronous on
+    ``stream`` (default: torch's current stream).  Returns the library's
+    return code after raising for any code but OK."""
+    torch = _torch()
+    dtype = torch.float64 if spec.dtype == "f64" else torch.float32
+    fp = require_state(f, spec, "f", dtype, cuda=False)
+    per = spec.dim * spec.nx * (spec.ny if spec.dim == 2 else 1)
+    up = require_tensor(u, "u", dtype, cuda=False)
+    if u.numel() % per or u.numel() == 0:
+        raise ValueError("u is not a whole number of slices")
+    sp = None
+    if status is not None:
+        sp = require_tensor(status, "status", torch.int32, numel=1,
+                            cuda=False)
+    require_cuda(f=f, u=u, status=status)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    d = _desc(spec, stream)
+    rc = load_library().lattice_step_noalloc(
+        ctypes.byref(d), fp, up, u.numel() // per, float(tau_p),
+        float(kappa), float(dt), int(nsteps), sp)
+    if rc != OK:
+        raise LatticeError(rc, strerror(rc))
+    return rc
+
+
 def velocity(spec: LatticeSpec, dt: float):
     """(dv, Vmax) computed by the library (host-only call)."""
     L = load_library()
@@ -904,4 +939,5 @@ __all__ = ["Lattice", "LatticeSpec", "LatticeError", "LatticeLibraryMissing",
            "require_tensor", "require_cuda", "require_state",
            "recommended_pitch",
            "Batch", "Member", "Mlp", "restrict", "load_library", "strerror",
-           "velocity", "EXPORTS", "MLP_NPARAMS"]
+           "velocity", "step_noalloc", "EXPORTS", "MLP_NPARAMS",
+           "NOALLOC_MAX_BYTES"]

@@ -102,6 +102,38 @@ def test_missing_library_fails_loudly(tmp_path):
         lattice._lib = saved
 
 
+def test_step_noalloc_host_checks_need_no_gpu(lib):
+    """The allocation-free step refuses bad calls on the host, before any
+    HIP call: a state past the static scratch (ETOOBIG), NULL or misaligned
+    pointers, and the Eq. 3 / Eq. 4 bounds that the arguments alone break."""
+    from paper_1508_02899_amd.lattice import (Desc, EDIFF, ECFL, EINVAL,
+                                              ETOOBIG, NOALLOC_MAX_BYTES)
+    d = Desc()
+    lib.lattice_desc_default(ctypes.byref(d))
+    d.dim, d.nx, d.ny, d.nv, d.dx = 2, 512, 512, 33, 0.0123
+    fake = ctypes.c_void_p(1 << 20)
+    assert 512 * 512 * 33 * 33 * 4 > NOALLOC_MAX_BYTES
+    assert lib.lattice_step_noalloc(ctypes.byref(d), fake, fake, 1, 1.0, 0.0,
+                                    0.05, 1, None) == ETOOBIG
+    d.nx, d.ny = 64, 32
+    assert lib.lattice_step_noalloc(ctypes.byref(d), None, fake, 1, 1.0, 0.0,
+                                    0.05, 1, None) == EINVAL
+    assert lib.lattice_step_noalloc(ctypes.byref(d), ctypes.c_void_p(2),
+                                    fake, 1, 1.0, 0.0, 0.05, 1, None) == EINVAL
+    assert lib.lattice_step_noalloc(ctypes.byref(d), fake, fake, 1, 1.0, 0.0,
+                                    0.05, 1, ctypes.c_void_p(3)) == EINVAL
+    # kappa dt / dv^2 = 1 >= 1/2 (Eq. 4); dv = dx / dt
+    dv = d.dx / 0.05
+    assert lib.lattice_step_noalloc(ctypes.byref(d), fake, fake, 1, 1.0,
+                                    dv * dv / 0.05, 0.05, 1, None) == EDIFF
+    # Vmax alone breaks Eq. 3 with a tiny tau_p
+    assert lib.lattice_step_noalloc(ctypes.byref(d), fake, fake, 1, 1e-9, 0.0,
+                                    0.05, 1, None) == ECFL
+    d.nv = 4
+    assert lib.lattice_step_noalloc(ctypes.byref(d), fake, fake, 1, 1.0, 0.0,
+                                    0.05, 1, None) == EINVAL
+
+
 def test_plane_pitch_recommendation_and_validation(lib):
     """lattice_plane_pitch pads the planes of 2D states whose plane spans a
     multiple of 64 KiB by 64 elements, and leaves other lattices

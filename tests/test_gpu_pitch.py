@@ -86,3 +86,19 @@ def test_padded_s1_and_copy():
     np.testing.assert_allclose(s_pad, s_flat, rtol=1e-6)
     assert np.isnan(_gaps(sp, buf)).all()
 
+
+def test_padded_no_alloc_step():
+    import torch
+    from paper_1508_02899_amd.lattice import step_noalloc
+    say("padded planes: step without allocation")
+    f0, u, p = make_case(2, 100, 17, ny=9, seed=741)
+    want = run_gpu(f0, u, p, 3)
+    spec = spec_for(f0, p, "f32")
+    sp, buf, f = _padded(spec, f0, 64)
+    status = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    step_noalloc(sp, f, torch.from_numpy(u).cuda(), p["tau_p"], p["kappa"],
+                 p["dt"], 3, status=status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
+    assert np.array_equal(f.cpu().numpy(), want)
+    assert np.isnan(_gaps(sp, buf)).all()
