@@ -116,8 +116,58 @@ def make_flow(w, nslices, dt, dtype):
                          dtype=dtype)
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def baseline_threads() -> int:
+    """Host threads for the threaded oracle leg: OMP_NUM_THREADS when set
+    (the GPU machine sets its CPU share there), else the usable cores."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        return int(env)
+    return len(os.sched_getaffinity(0))
+
+
 def cpu_baseline(w, name, dx, dv, dt, tau_p):
-    """The FP64 oracle, untouched, on a bounded sample of the workload."""
+    """The FP64 oracle on a bounded sample of the workload: its plain
+    single-threaded build in this process, then the same source built with
+    OpenMP over sites, in a process of its own with OMP_NUM_THREADS set."""
+    import subprocess
+    one = cpu_sample(w, dx, dv, dt, tau_p)
+    n = baseline_threads()
+    out = {"value": one["value"], "unit": "GCUPS", "cores": 1,
+           "kind": "oracle", "sample": one["sample"],
+           "seconds": one["seconds"], "value_1thread": one["value"],
+           "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+           "affinity_cores": len(os.sched_getaffinity(0))}
+    if n > 1:
+        import oracle
+        env = dict(os.environ, ORACLE_LIB=oracle.OMP_SO,
+                   OMP_NUM_THREADS=str(n))
+        args = [sys.executable, os.path.abspath(__file__), "--cpu-sample",
+                json.dumps(dict(w=w, dx=dx, dv=dv, dt=dt, tau_p=tau_p))]
+        r = subprocess.run(args, env=env, capture_output=True, text=True,
+                           timeout=600)
+        if r.returncode == 0:
+            many = json.loads(r.stdout.strip().splitlines()[-1])
+            out.update(value=many["value"], cores=n, seconds=many["seconds"],
+                       value_nthreads=many["value"], threads=n)
+        else:
+            log("bench: threaded oracle leg failed:", r.stderr[-500:])
+    return out
+
+
+def cpu_sample(w, dx, dv, dt, tau_p):
+    """Time the oracle (whichever build ORACLE_LIB selects) on the bounded
+    sample of the workload."""
     import numpy as np
 
     import oracle
@@ -145,8 +195,8 @@ def cpu_baseline(w, name, dx, dv, dt, tau_p):
                 dx=dx, tau_p=tau_p, kappa=w["kappa"], dt=dt, nsteps=steps,
                 s=w["s"])
     el = time.perf_counter() - t0
-    return {"value": cells * steps / el / 1e9, "unit": "GCUPS", "cores": 1,
-            "kind": "oracle", "sample": sample, "seconds": round(el, 3)}
+    return {"value": cells * steps / el / 1e9, "sample": sample,
+            "seconds": round(el, 3)}
 
 
 def batch_members(count, nsteps):
@@ -601,7 +651,13 @@ def main():
                          "and coarse workloads)")
     ap.add_argument("--command", default="",
                     help="with --summarize: the command line that made them")
+    ap.add_argument("--cpu-sample", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_sample:  # the threaded oracle leg of the CPU baseline
+        p = json.loads(args.cpu_sample)
+        print(json.dumps(cpu_sample(p["w"], p["dx"], p["dv"], p["dt"],
+                                    p["tau_p"])))
+        return 0
     if args.summarize:
         return summarize(args)
     if args.summarize_trace:
@@ -691,25 +747,31 @@ def main():
     if W:
         run_steps(0, W)
         lat.sync()
-    # Launch durations: the K launches of a second pass of the same steps
-    # right after the timed region, timed back to back by one event pair
-    # on the library's stream (torch's current one).  Events around every
-    # launch inside the timed region cost time themselves: measured on
-    # configuration 3, 464 us per launch that way against 457 us back to
-    # back, and a 1.5 % lower whole-run rate; a 1D step lasts a few us and
-    # an event pair per launch would add its own latency.
+    # Launch durations over the timed region itself: one event pair on the
+    # library's stream (torch's current one) around the K steps, recorded
+    # before the final moments (the span holds the K step launches and the
+    # device CFL check of their flow slices, about 0.2 % of it).  Events
+    # around every launch would cost time themselves (on the 2D workload
+    # 464 us per launch against 457 us back to back).  A second pass of the
+    # same steps right after the timed region is timed the same way and
+    # reported beside it: the first pass of a run meets the chip's power
+    # management settling (launches slow down after a few ms of this load
+    # and recover), which the second pass largely has behind it.
     torch.cuda.synchronize()
     lat.profile(False)
     ev0 = torch.cuda.Event(enable_timing=True)
+    evk = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     ev0.record()
     run_steps(W, K)
+    evk.record()
     m1 = lat.moments(f, dt)
     ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ev_ms = ev0.elapsed_time(ev1)
+    kern_ms = ev0.elapsed_time(evk)
     ev2 = torch.cuda.Event(enable_timing=True)
     ev3 = torch.cuda.Event(enable_timing=True)
     ev2.record()
@@ -719,7 +781,7 @@ def main():
     lat.sync()
     # a 2D step is nsub passes (the later ones collision only), each
     # reading and writing the whole state; a 1D step is one launch
-    kern_ms, launches = ev2.elapsed_time(ev3), K * (nsub if dim == 2 else 1)
+    kern2_ms, launches = ev2.elapsed_time(ev3), K * (nsub if dim == 2 else 1)
     if args.copy_calibration:
         g = spec.empty_state()
         lat.copy_state(g, f)
@@ -733,8 +795,9 @@ def main():
             f"{2 * cells * elem / el / 1e9:.1f} GB/s")
         del g
     lat.close()
-    log(f"bench: wall {wall * 1e3:.2f} ms, events {ev_ms:.2f} ms, kernel "
-        f"{kern_ms:.2f} ms over {launches} launches")
+    log(f"bench: wall {wall * 1e3:.2f} ms, events {ev_ms:.2f} ms, steps "
+        f"{kern_ms:.2f} ms over {launches} launches (second pass "
+        f"{kern2_ms:.2f} ms)")
 
     sec = ev_ms / 1e3
     value = cells * K / sec / 1e9
@@ -772,6 +835,7 @@ def main():
             "nsub": nsub,
             "cfl": round(cfl, 4),
             "mass_drift_rel": mass_drift,
+            "final_moments_ms": round(ev_ms - kern_ms, 4),
             "hbm_frac_wall": round(2 * cells * elem * K / sec / 1e9
                                    / HBM_PEAK_GBS, 4),
         },
@@ -784,11 +848,14 @@ def main():
             "traffic": traffic,
             "kernel": step_kernel(dim, n, nv, w["dtype"]),
             "avg_launch_us": round(avg_launch_s * 1e6, 3),
-            "launch_timing": ("one HIP event pair around the back-to-back "
-                              "launches of a second pass of the same K steps "
-                              "after the timed region"
-                              + (" (the pass includes the flow synthesis "
-                                 "kernels)" if device_flow else "")),
+            "launch_timing": ("one HIP event pair around the K steps of the "
+                              "timed region (before its final moments; the "
+                              "span includes the device CFL check of the "
+                              "flow slices"
+                              + (" and the flow synthesis kernels"
+                                 if device_flow else "") + ")"),
+            "second_pass_avg_launch_us": round(
+                kern2_ms * 1e3 / max(launches, 1), 3),
             "algorithmic_bytes_per_launch": algo_bytes,
         },
     }

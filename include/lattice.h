@@ -244,6 +244,20 @@ int lattice_density(lattice_t* L, const void* f, double dt, double* rho);
 int lattice_rho_r2(lattice_t* L, const double* rho, int levels, double* out);
 
 /*
+ * Distance-averaged relative error of <rho_r^2> (Sec. 4.2.1, Eqs. 14-15:
+ * the r dr average over the scales of |<rho_r^2>_A - <rho_r^2>_B| relative
+ * to that of <rho_r^2>_B), on the tiling scales r_k = 2^k dx of
+ * lattice_rho_r2 (k = 0..levels-1): with weights r_k dr_k = r_k^2 on that
+ * log-spaced grid,
+ *   *err = sum_k r_k^2 |a[k] - b[k]| / sum_k r_k^2 |b[k]|.
+ * a, b: host, levels doubles (e.g. two lattice_rho_r2 outputs).  Host-only.
+ * EINVAL on NULL pointers, levels outside [1, 32], dx <= 0; ENONFINITE
+ * when the denominator is zero or a value is not finite.
+ */
+int lattice_rho_r2_error(const double* a, const double* b, int levels,
+                         double dx, double* err);
+
+/*
  * Eulerian first-order structure function of the particle velocity (Eq. 11,
  * Sec. 3.1; its scaling exponent is studied in Secs. 3.2 and 4.2.1):
  *   S1(r) = <sum_{j,j'} f(x,v_j) f(x+r,v_j') |v_j - v_j'|>_x

@@ -30,13 +30,22 @@ SCHEMES = {"upwind": 0, "koren": 1}
 _lib = None
 
 
+# the same source built with OpenMP: only the benchmark's CPU baseline loads
+# it (through ORACLE_LIB, in a process of its own), to time the oracle on
+# several host cores; the tests use the single-threaded build
+OMP_SO = os.path.join(_HERE, "liboracle_omp.so")
+
+
 def build() -> str:
-    """Compile oracle.c into liboracle.so (plain -O2, no fast-math)."""
-    tmp = _SO + ".tmp"
-    subprocess.check_call(
-        ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
-    )
-    os.replace(tmp, _SO)
+    """Compile oracle.c into liboracle.so (plain -O2, no fast-math, one
+    thread) and liboracle_omp.so (the same with OpenMP)."""
+    for so, extra in ((os.path.join(_HERE, "liboracle.so"), []),
+                      (OMP_SO, ["-fopenmp"])):
+        tmp = so + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c99", "-fPIC", "-shared",
+             "-Wno-unknown-pragmas", *extra, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, so)
     return _SO
 
 

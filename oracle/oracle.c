@@ -132,10 +132,12 @@ void orc_stream(int dim, long nx, long ny, int nv, int s, const double* f,
   long h = (nv - 1) / 2;
   long sites = nx * ny;
   if (dim == 1) {
+#pragma omp parallel for schedule(static)
     for (long j = 0; j < nv; ++j)
       for (long x = 0; x < nx; ++x)
         g[j * nx + x] = f[j * nx + wrap(x - s * (j - h), nx)];
   } else {
+#pragma omp parallel for schedule(static)
     for (long jy = 0; jy < nv; ++jy)
       for (long jx = 0; jx < nv; ++jx) {
         long jv = jy * nv + jx;
@@ -161,8 +163,15 @@ static void collide(int dim, long nx, long ny, int nv, double dv, int scheme,
   long h = (nv - 1) / 2;
   long sites = nx * ny;
   double D = kappa * dts / (dv * dv);
+  /* Sites are independent.  A build with OpenMP (used only to time the
+   * CPU baseline) spreads them over threads, each with its own line
+   * buffers; the plain build runs the same loop on one thread.  The
+   * arithmetic of a site does not depend on the thread that runs it. */
+#pragma omp parallel
+  {
   double* line = (double*)malloc(sizeof(double) * (size_t)nv);
   double* nu = (double*)malloc(sizeof(double) * (size_t)nv);
+#pragma omp for schedule(static)
   for (long site = 0; site < sites; ++site) {
     if (dim == 1) {
       for (int j = 0; j < nv; ++j) {
@@ -216,6 +225,7 @@ static void collide(int dim, long nx, long ny, int nv, double dv, int scheme,
   }
   free(line);
   free(nu);
+  }
 }
 
 /*

@@ -226,6 +226,7 @@ def errors(tracks: dict, ref: str, dx: float, from_step: int = 0):
     scales r = 2^k dx, the discrete form of the r dr average of Sec. 4.2.1).
     """
     import numpy as np
+    from .lattice import rho_r2_error
     R = tracks[ref]
     sel = [i for i, s in enumerate(R.steps) if s >= from_step]
     out = {}
@@ -233,12 +234,7 @@ def errors(tracks: dict, ref: str, dx: float, from_step: int = 0):
         if k == ref:
             continue
         ev = [abs(T.variance[i] - R.variance[i]) / R.variance[i] for i in sel]
-        er = []
-        for i in sel:
-            a, b = np.asarray(T.rho_r2[i]), np.asarray(R.rho_r2[i])
-            r = dx * 2.0 ** np.arange(len(b))
-            wgt = r * r
-            er.append(float(np.sum(wgt * np.abs(a - b)) / np.sum(wgt * b)))
+        er = [rho_r2_error(T.rho_r2[i], R.rho_r2[i], dx) for i in sel]
         out[k] = {"variance": float(np.mean(ev)), "rho_r2": float(np.mean(er))}
     return out
 

@@ -547,6 +547,22 @@ int lattice_rho_r2(lattice_t* L, const double* rho, int levels, double* out) {
   return LATTICE_OK;
 }
 
+int lattice_rho_r2_error(const double* a, const double* b, int levels,
+                         double dx, double* err) {
+  if (!a || !b || !err || levels < 1 || levels > lat::kRhoMaxLevels ||
+      !(dx > 0.0) || !isfinite(dx))
+    return LATTICE_EINVAL;
+  double num = 0.0, den = 0.0, r = dx;
+  for (int k = 0; k < levels; ++k, r *= 2.0) {
+    const double w = r * r;  // r dr on the grid r_k = 2^k dx
+    num += w * fabs(a[k] - b[k]);
+    den += w * fabs(b[k]);
+  }
+  *err = num / den;
+  if (!(den > 0.0) || !isfinite(*err)) return LATTICE_ENONFINITE;
+  return LATTICE_OK;
+}
+
 int lattice_stability(lattice_t* L, const void* u, int64_t n_u_slices,
                       double tau_p, double kappa, double dt, double* out) {
   if (!L) return LATTICE_EINVAL;

@@ -30,6 +30,7 @@ EXPORTS = (
     "lattice_collide", "lattice_step_noalloc",
     "lattice_moments", "lattice_density", "lattice_stability",
     "lattice_copy_state", "lattice_sync", "lattice_profile", "lattice_rho_r2",
+    "lattice_rho_r2_error",
     "lattice_flow1d_modes", "lattice_flow2d_modes", "lattice_s1",
     "lattice_profile_read", "lattice_destroy", "lattice_strerror",
     "lattice_last_error", "lattice_batch_init", "lattice_batch_layout",
@@ -126,6 +127,9 @@ def load_library(path: str = LIB_PATH):
                                     ctypes.POINTER(dbl)]
     L.lattice_copy_state.argtypes = [vp, vp, vp]
     L.lattice_rho_r2.argtypes = [vp, vp, i32, ctypes.POINTER(dbl)]
+    L.lattice_rho_r2_error.argtypes = [ctypes.POINTER(dbl),
+                                       ctypes.POINTER(dbl), i32, dbl,
+                                       ctypes.POINTER(dbl)]
     L.lattice_flow1d_modes.argtypes = [vp, i32, vp, i64, vp]
     L.lattice_s1.argtypes = [vp, vp, dbl, i32, ctypes.POINTER(i32),
                              ctypes.POINTER(dbl)]
@@ -920,6 +924,24 @@ def step_noalloc(spec: LatticeSpec, f, u, tau_p: float, kappa: float,
     return rc
 
 
+def rho_r2_error(a, b, dx: float) -> float:
+    """Distance-averaged relative error of <rho_r^2>_a against <rho_r^2>_b
+    on the tiling scales r = 2^k dx (lattice_rho_r2_error)."""
+    import numpy as np
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    b = np.ascontiguousarray(np.asarray(b, dtype=np.float64))
+    if a.shape != b.shape or a.ndim != 1:
+        raise ValueError("a and b must be 1-D arrays of one length")
+    out = ctypes.c_double()
+    pd = ctypes.POINTER(ctypes.c_double)
+    rc = load_library().lattice_rho_r2_error(a.ctypes.data_as(pd),
+                                             b.ctypes.data_as(pd), a.size,
+                                             float(dx), ctypes.byref(out))
+    if rc != OK:
+        raise LatticeError(rc, strerror(rc))
+    return out.value
+
+
 def velocity(spec: LatticeSpec, dt: float):
     """(dv, Vmax) computed by the library (host-only call)."""
     L = load_library()
@@ -939,5 +961,5 @@ __all__ = ["Lattice", "LatticeSpec", "LatticeError", "LatticeLibraryMissing",
            "require_tensor", "require_cuda", "require_state",
            "recommended_pitch",
            "Batch", "Member", "Mlp", "restrict", "load_library", "strerror",
-           "velocity", "step_noalloc", "EXPORTS", "MLP_NPARAMS",
+           "velocity", "step_noalloc", "rho_r2_error", "EXPORTS", "MLP_NPARAMS",
            "NOALLOC_MAX_BYTES"]

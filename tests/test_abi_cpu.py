@@ -172,3 +172,31 @@ def test_plane_pitch_recommendation_and_validation(lib):
         assert (rc == 0) == ok, pitch
     d.plane_pitch = 0
     assert lib.lattice_plane_pitch(None, ctypes.byref(p)) == EINVAL
+
+
+def test_rho_r2_error_matches_the_oracle_and_closed_forms(lib):
+    """lattice_rho_r2_error (host-only) against the oracle's distance-
+    averaged error on random curves, and on hand cases: equal curves give
+    0; a curve off by the same fraction at every scale gives that
+    fraction; a difference at one scale only is weighted by r^2."""
+    import numpy as np
+    from oracle import observables as O
+    from paper_1508_02899_amd.lattice import rho_r2_error, LatticeError
+    rng = np.random.default_rng(5)
+    for levels in (1, 4, 9):
+        a = 1 + rng.random(levels) * 3
+        b = 1 + rng.random(levels) * 3
+        dx = 2 * np.pi / 256
+        assert rho_r2_error(a, b, dx) == pytest.approx(
+            O.distance_averaged_error(a, b, dx), rel=1e-14)
+    b = np.array([4.0, 2.5, 1.6, 1.1])
+    assert rho_r2_error(b, b, 0.1) == 0.0
+    assert rho_r2_error(1.03 * b, b, 0.1) == pytest.approx(0.03, rel=1e-13)
+    a = b.copy()
+    a[2] += 0.5     # only r = 4 dx differs: 16 * 0.5 / (4 + 4*2.5 + 16*1.6 + 64*1.1)
+    assert rho_r2_error(a, b, 1.0) == pytest.approx(
+        16 * 0.5 / (4 + 4 * 2.5 + 16 * 1.6 + 64 * 1.1), rel=1e-14)
+    with pytest.raises(LatticeError):
+        rho_r2_error(b, np.zeros(4), 0.1)
+    with pytest.raises(LatticeError):
+        rho_r2_error(b, b, -1.0)
