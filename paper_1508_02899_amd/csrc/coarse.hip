@@ -77,14 +77,40 @@ __device__ __forceinline__ bf16x4 pack4(float a, float b, float c, float d) {
   return __builtin_bit_cast(bf16x4, w);
 }
 
+// 16x16x32 bf16 matrix-core product (gfx950), FP32 accumulation: A lane l
+// holds row l%16, K indices 8(l/16)+i; B lane l holds column l%16, the
+// same K indices; the result lane l holds rows 4(l/16)+r of column l%16.
+typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ f32x4 mfma32(s16x8 a, s16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+      __builtin_bit_cast(bf16x8v, a), __builtin_bit_cast(bf16x8v, b), c, 0, 0,
+      0);
+}
+// K index i (0..7) of K step kk for lane group g -> unit of the 64-wide
+// hidden layer (two stacked output tiles, see above)
+__device__ __forceinline__ int kunit(int kk, int g, int i) {
+  return 32 * kk + (i < 4 ? 4 * g + i : 16 + 4 * g + (i - 4));
+}
+__device__ __forceinline__ short bfs(float f) { return (short)f2bf(f); }
+// two stacked 16-row output tiles as one 16x16x32 K operand
+__device__ __forceinline__ s16x8 cat8(bf16x4 p, bf16x4 q) {
+  return s16x8{p[0], p[1], p[2], p[3], q[0], q[1], q[2], q[3]};
+}
+
 // The network in matrix-core form.  16 inputs (faces) per wavefront pass;
-// each layer is computed transposed, D = W^T X^T, so that the 16x16x16
-// MFMA result layout (lane l: rows 4(l/16)+i, column l%16) is exactly the
-// B-operand layout of the next layer (lane l: k = 4(l/16)+i, column l%16).
+// each layer is computed transposed, D = W^T X^T.  Layer 1 (K = 8
+// features) is a 16x16x16 product whose B operand is the input; the 64
+// hidden units of a layer come out as four 16x16 tiles (lane l: rows
+// 4(l/16)+r of column l%16), and two of them (units u and u+16 of a 32-unit
+// K step) are the B operand of a 16x16x32 product when its K index
+// 8(l/16)+i names unit kunit(kk, l/16, i); the weight operands are loaded
+// in that K order.
 struct MlpRegs {
   bf16x4 a1[4];      // W1^T tiles (units 16u.., features)
-  bf16x4 a2[4][4];   // W2^T tiles [unit tile][k step]
-  bf16x4 a3[4];      // w3 as row 0 of a 16-row A operand, per k step
+  s16x8 a2[4][2];    // W2^T tiles [unit tile][K step of 32 units]
+  s16x8 a3[2];       // w3 as row 0 of a 16-row A operand, per K step
   float b1[4][4], b2[4][4];  // biases of this lane's D rows
   float b3;
 };
@@ -101,12 +127,11 @@ __device__ void load_mlp(MlpRegs& R, const float* __restrict__ P,
       R.a1[u][i] = k < kNF ? (short)wq[kOffW1 + k * kNH + unit] : (short)0;
     }
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk)
+    for (int kk = 0; kk < 2; ++kk)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int k = 16 * kk + 4 * ks + i, unit = 16 * u + col;
-        R.a2[u][kk][i] = (short)wq[kOffW2 + k * kNH + unit];
-      }
+      for (int i = 0; i < 8; ++i)
+        R.a2[u][kk][i] =
+            (short)wq[kOffW2 + kunit(kk, ks, i) * kNH + 16 * u + col];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       R.b1[u][i] = P[kOffB1 + 16 * u + 4 * ks + i];
@@ -114,11 +139,11 @@ __device__ void load_mlp(MlpRegs& R, const float* __restrict__ P,
     }
   }
 #pragma unroll
-  for (int kk = 0; kk < 4; ++kk)
+  for (int kk = 0; kk < 2; ++kk)
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-      R.a3[kk][i] = col == 0 ? (short)wq[kOffW3 + 16 * kk + 4 * ks + i]
-                             : (short)0;
+    for (int i = 0; i < 8; ++i)
+      R.a3[kk][i] =
+          col == 0 ? (short)wq[kOffW3 + kunit(kk, ks, i)] : (short)0;
   R.b3 = P[kOffB3];
 }
 
@@ -138,12 +163,14 @@ __device__ __forceinline__ float mlp_forward(const MlpRegs& R, bf16x4 x) {
   for (int u = 0; u < 4; ++u) {
     f32x4 d = {R.b2[u][0], R.b2[u][1], R.b2[u][2], R.b2[u][3]};
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) d = mfma16(R.a2[u][kk], h1[kk], d);
+    for (int kk = 0; kk < 2; ++kk)
+      d = mfma32(R.a2[u][kk], cat8(h1[2 * kk], h1[2 * kk + 1]), d);
     h2[u] = pack4(gelu(d[0]), gelu(d[1]), gelu(d[2]), gelu(d[3]));
   }
   f32x4 y = {R.b3, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int kk = 0; kk < 4; ++kk) y = mfma16(R.a3[kk], h2[kk], y);
+  for (int kk = 0; kk < 2; ++kk)
+    y = mfma32(R.a3[kk], cat8(h2[2 * kk], h2[2 * kk + 1]), y);
   return y[0];
 }
 
@@ -165,12 +192,14 @@ __device__ __forceinline__ float mlp_forward_lds(const MlpRegs& R,
   for (int u = 0; u < 4; ++u) {
     f32x4 d = *(const f32x4*)(b2s + 16 * u + 4 * ks);
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) d = mfma16(R.a2[u][kk], h1[kk], d);
+    for (int kk = 0; kk < 2; ++kk)
+      d = mfma32(R.a2[u][kk], cat8(h1[2 * kk], h1[2 * kk + 1]), d);
     h2[u] = pack4(gelu(d[0]), gelu(d[1]), gelu(d[2]), gelu(d[3]));
   }
   f32x4 y = {R.b3, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int kk = 0; kk < 4; ++kk) y = mfma16(R.a3[kk], h2[kk], y);
+  for (int kk = 0; kk < 2; ++kk)
+    y = mfma32(R.a3[kk], cat8(h2[2 * kk], h2[2 * kk + 1]), y);
   return y[0];
 }
 
@@ -519,156 +548,330 @@ __global__ __launch_bounds__(256) void k_flux_samples_nat(
 // --------------------------------------------------------------- training
 // Gradients of L = sum_i w_i (y_i - t_i)^2 / sum_i w_i, weights and layer
 // inputs rounded to bf16 as in the matrix-core forward (the rounding passed
-// straight through).  One wavefront per block walks its share of samples
-// 64 at a time: per-sample activations in LDS, then every lane accumulates
-// its own parameters (p = lane + 64 m) over the 64 samples.
-constexpr int kOwn = (kNParams + 63) / 64;  // 76 parameters per lane
+// straight through).
+// ---------------------------------------------------- training, matrix cores
+// The same gradients on the matrix cores (gfx950 v_mfma_f32_16x16x32_bf16,
+// FP32 accumulation).  Every product pairs an operand that is a bf16 value
+// by definition of the network (the rounded weights, layer inputs and
+// activations) with one that is FP32 in the definition (the backward
+// signals dz); the latter enters as two bf16 operands, hi = bf16(dz) and
+// lo = bf16(dz - hi), i.e. about 16 significant bits, so the products match
+// the FP32 arithmetic of the definition to ~2^-17 relative.
+//
+// A wavefront takes 32 samples at a time (two 16-sample column tiles).  The
+// forward and the backward-data products run transposed (units x samples,
+// as in the inference kernel): the 16x16 output tile of one layer, lane l
+// holding rows 4(l/16)+r, r < 4, of column l%16, is the B operand of the
+// next product once two tiles (rows u and u+16 of a 32-row K step) are
+// read as K indices 8(l/16)+i, i < 8 -- the weight operand is loaded in the
+// same K order.  The weight gradients sum over the samples (K = the 32
+// samples of the step): the activations and signals go through a
+// per-wavefront LDS transpose ([unit][sample], bf16).  Each wavefront writes
+// one row of per-parameter sums (then the block order reduction).
 
-__global__ __launch_bounds__(64) void k_mlp_grad(
+constexpr int kGS = 32;                 // samples per wavefront step
+constexpr int kGP = kGS + 8;            // LDS row pitch (bf16), 80 bytes
+constexpr int kGWaves = 4;              // wavefronts per block
+// per wavefront: H1 / (X^T, 16 rows) and the hi / lo signals, [row][sample]
+constexpr int kGLds = (kNH + kNH + kNH + 16) * kGP;
+
+__global__ __launch_bounds__(64 * kGWaves) void k_mlp_grad_mfma(
     const float* __restrict__ P, const float* __restrict__ X,
     const float* __restrict__ T, const float* __restrict__ Wt, int64_t n,
-    float inv_wsum, float* __restrict__ partial, int nblocks) {
-  __shared__ float w1[kNF * kNH], b1[kNH], w2[kNH * kNH], b2[kNH], w3[kNH];
-  __shared__ float sx[64][kNF + 1];
-  __shared__ float sh1[64][kNH + 1], sh2[64][kNH + 1];
-  __shared__ float sd1[64][kNH + 1], sd2[64][kNH + 1];
-  __shared__ float sdy[64];
-  __shared__ float sl[64];
-  __shared__ float sacc[kOwn][64];  // this block's gradient, lane-owned
-  const int tid = (int)threadIdx.x;
-  for (int m = 0; m < kOwn; ++m) sacc[m][tid] = 0.f;
-  for (int i = tid; i < kNF * kNH; i += 64) w1[i] = qbf(P[kOffW1 + i]);
-  for (int i = tid; i < kNH * kNH; i += 64) w2[i] = qbf(P[kOffW2 + i]);
-  for (int i = tid; i < kNH; i += 64) {
-    b1[i] = P[kOffB1 + i];
-    b2[i] = P[kOffB2 + i];
-    w3[i] = qbf(P[kOffW3 + i]);
+    float inv_wsum, float* __restrict__ partial, int nrows) {
+  __shared__ __attribute__((aligned(16))) short lds[kGWaves * kGLds];
+  const int wv = (int)threadIdx.x >> 6;
+  const int row = (int)blockIdx.x * kGWaves + wv;  // partial row of this wave
+  if (row >= nrows) return;  // wave-uniform; no block barrier below
+  short* sH = lds + wv * kGLds;           // [64][kGP]: h1, later unused
+  short* sHi = sH + kNH * kGP;            // [64][kGP]: dz2 hi, then dz1 hi
+  short* sLo = sHi + kNH * kGP;           // [64][kGP]: dz2 lo, then dz1 lo
+  short* sX = sLo + kNH * kGP;            // [16][kGP]: x^T, row 8 = ones
+  const int l = (int)threadIdx.x & 63;
+  const int c = l & 15, g = l >> 4;
+
+  // ---- weights (bf16 as the network defines them) and biases
+  bf16x4 a1[4];          // W1^T, K = features 4g + r
+  s16x8 a2[4][2];        // W2^T: rows = output units, K = input units
+  s16x8 a2t[4][2];       // W2:   rows = input units,  K = output units
+  float w3q[4][4], b1r[4][4], b2r[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int k = 4 * g + r;
+      a1[u][r] = k < kNF ? bfs(P[kOffW1 + k * kNH + 16 * u + c]) : (short)0;
+      const int unit = 16 * u + 4 * g + r;
+      w3q[u][r] = qbf(P[kOffW3 + unit]);
+      b1r[u][r] = P[kOffB1 + unit];
+      b2r[u][r] = P[kOffB2 + unit];
+    }
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int ku = kunit(kk, g, i);
+        a2[u][kk][i] = bfs(P[kOffW2 + ku * kNH + 16 * u + c]);
+        a2t[u][kk][i] = bfs(P[kOffW2 + (16 * u + c) * kNH + ku]);
+      }
   }
   const float b3 = P[kOffB3];
-  __syncthreads();
-  float lsum = 0.f;
-  const int64_t lo = n * blockIdx.x / nblocks, hi = n * (blockIdx.x + 1) / nblocks;
-  for (int64_t base = lo; base < hi; base += 64) {
-    const int64_t i = base + tid;
-    const bool valid = i < hi;
-    float x[kNF];
+  // rows 8..15 of x^T: ones (row 8, for the b1 gradient) and zeros
+  for (int i = l; i < 8 * kGP; i += 64)
+    sX[8 * kGP + i] = (i < kGP) ? bfs(1.0f) : (short)0;
+
+  f32x4 gW2[4][4], gW1[4];
 #pragma unroll
-    for (int k = 0; k < kNF; ++k) x[k] = valid ? qbf(X[i * kNF + k]) : 0.f;
-    const float t = valid ? T[i] : 0.f, w = valid ? Wt[i] : 0.f;
-    // forward
-    float z2[kNH];
+  for (int a = 0; a < 4; ++a) {
+    gW1[a] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int j = 0; j < kNH; ++j) z2[j] = b2[j];
-    for (int j = 0; j < kNH; ++j) {
-      float z = b1[j];
+    for (int b = 0; b < 4; ++b) gW2[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+  float gb2[4][4] = {}, gw3[4][4] = {};
+  float gb3 = 0.f, lsum = 0.f;
+
+  const int64_t lo = n * row / nrows, hi = n * (row + 1) / nrows;
+  for (int64_t s0 = lo; s0 < hi; s0 += kGS) {
+    // ---- inputs of the two column tiles (sample s0 + 16 t + c)
+    bf16x4 xb[2];
+    float tt[2], ww[2];
 #pragma unroll
-      for (int k = 0; k < kNF; ++k) z += x[k] * w1[k * kNH + j];
-      float dg;
-      const float h = qbf(gelu_d(z, &dg));
-      sh1[tid][j] = h;
-      sd1[tid][j] = dg;  // gelu'(z1), replaced by dz1 below
+    for (int t = 0; t < 2; ++t) {
+      const int64_t i = s0 + 16 * t + c;
+      const bool ok = i < hi;
+      float xf[4] = {0.f, 0.f, 0.f, 0.f};
+      if (ok && g < 2)
 #pragma unroll
-      for (int q = 0; q < kNH; ++q) z2[q] += h * w2[j * kNH + q];
-    }
-    float y = b3;
-    float dz2[kNH];
+        for (int r = 0; r < 4; ++r) xf[r] = X[i * kNF + 4 * g + r];
+      tt[t] = ok ? T[i] : 0.f;
+      ww[t] = ok ? Wt[i] : 0.f;
 #pragma unroll
-    for (int j = 0; j < kNH; ++j) {
-      float dg;
-      const float h = qbf(gelu_d(z2[j], &dg));
-      sh2[tid][j] = h;
-      y += h * w3[j];
-      dz2[j] = dg;
-    }
-    const float e = y - t;
-    lsum += w * e * e * inv_wsum;
-    const float dy = 2.0f * w * e * inv_wsum;
-    sdy[tid] = dy;
-#pragma unroll
-    for (int j = 0; j < kNH; ++j) {
-      dz2[j] *= dy * w3[j];
-      sd2[tid][j] = dz2[j];
-    }
-    for (int j = 0; j < kNH; ++j) {
-      float dh = 0.f;
-#pragma unroll
-      for (int q = 0; q < kNH; ++q) dh += dz2[q] * w2[j * kNH + q];
-      sd1[tid][j] = dh * sd1[tid][j];
-    }
-#pragma unroll
-    for (int k = 0; k < kNF; ++k) sx[tid][k] = x[k];
-    __syncthreads();
-    // accumulate this lane's parameters over the 64 samples
-    for (int m = 0; m < kOwn; ++m) {
-      const int p = tid + 64 * m;
-      float s = 0.f;
-      if (p < kOffB1) {  // W1[k][j]
-        const int k = p / kNH, j = p - k * kNH;
-        for (int b = 0; b < 64; ++b) s += sx[b][k] * sd1[b][j];
-      } else if (p < kOffW2) {  // b1[j]
-        const int j = p - kOffB1;
-        for (int b = 0; b < 64; ++b) s += sd1[b][j];
-      } else if (p < kOffB2) {  // W2[i][j]
-        const int q = p - kOffW2, ii = q / kNH, j = q - ii * kNH;
-        for (int b = 0; b < 64; ++b) s += sh1[b][ii] * sd2[b][j];
-      } else if (p < kOffW3) {  // b2[j]
-        const int j = p - kOffB2;
-        for (int b = 0; b < 64; ++b) s += sd2[b][j];
-      } else if (p < kOffB3) {  // w3[j]
-        const int j = p - kOffW3;
-        for (int b = 0; b < 64; ++b) s += sh2[b][j] * sdy[b];
-      } else if (p == kOffB3) {
-        for (int b = 0; b < 64; ++b) s += sdy[b];
+      for (int r = 0; r < 4; ++r) {
+        xb[t][r] = bfs(xf[r]);
+        if (g < 2) sX[(4 * g + r) * kGP + 16 * t + c] = xb[t][r];
       }
-      sacc[m][tid] += s;
     }
-    __syncthreads();
+    // ---- layer 1 (K = 8 features, 16x16x16) and GELU
+    float gd1[4][2][4];
+    bf16x4 h1[4][2];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const f32x4 b = {b1r[u][0], b1r[u][1], b1r[u][2], b1r[u][3]};
+        const f32x4 z = mfma16(a1[u], xb[t], b);
+        float h[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          float dg;
+          h[r] = gelu_d(z[r], &dg);
+          gd1[u][t][r] = dg;
+        }
+        h1[u][t] = pack4(h[0], h[1], h[2], h[3]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          sH[(16 * u + 4 * g + r) * kGP + 16 * t + c] = h1[u][t][r];
+      }
+    // ---- layer 2 (K = 64, 16x16x32) and GELU
+    float gd2[4][2][4], h2[4][2][4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        f32x4 z = {b2r[m][0], b2r[m][1], b2r[m][2], b2r[m][3]};
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+          z = mfma32(a2[m][kk], cat8(h1[2 * kk][t], h1[2 * kk + 1][t]), z);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          float dg;
+          h2[m][t][r] = qbf(gelu_d(z[r], &dg));
+          gd2[m][t][r] = dg;
+        }
+      }
+    // ---- output, loss, dy (each sample's four lane groups agree)
+    float dy[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      float part = 0.f;
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) part += h2[m][t][r] * w3q[m][r];
+      part += __shfl_xor(part, 16);
+      part += __shfl_xor(part, 32);
+      const float y = b3 + part;
+      const float e = y - tt[t];
+      if (g == 0) {
+        lsum += ww[t] * e * e * inv_wsum;
+      }
+      dy[t] = 2.0f * ww[t] * e * inv_wsum;
+      if (g == 0) gb3 += dy[t];
+    }
+    // ---- backward through layer 3 and the second GELU
+    s16x8 dhi[4][2], dlo[4][2];  // dz2 as K operands: [K step][t] below
+    float dz2[4][2][4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float d = w3q[m][r] * dy[t] * gd2[m][t][r];
+          dz2[m][t][r] = d;
+          gb2[m][r] += d;
+          gw3[m][r] += h2[m][t][r] * dy[t];
+          const short hs = bfs(d);
+          const short ls = bfs(d - bf2f((uint16_t)hs));
+          sHi[(16 * m + 4 * g + r) * kGP + 16 * t + c] = hs;
+          sLo[(16 * m + 4 * g + r) * kGP + 16 * t + c] = ls;
+        }
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const float d = dz2[2 * kk + (i >> 2)][t][i & 3];
+          const short hs = bfs(d);
+          dhi[kk][t][i] = hs;
+          dlo[kk][t][i] = bfs(d - bf2f((uint16_t)hs));
+        }
+    // ---- weight gradient of layer 2: sum over the 32 samples
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const s16x8 ah = *(const s16x8*)(sH + (16 * a + c) * kGP + 8 * g);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const s16x8 bh = *(const s16x8*)(sHi + (16 * b + c) * kGP + 8 * g);
+        const s16x8 bl = *(const s16x8*)(sLo + (16 * b + c) * kGP + 8 * g);
+        gW2[a][b] = mfma32(ah, bh, gW2[a][b]);
+        gW2[a][b] = mfma32(ah, bl, gW2[a][b]);
+      }
+    }
+    // ---- backward through layer 2 (K = 64 output units) and the first GELU
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        f32x4 dh = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+          dh = mfma32(a2t[m][kk], dhi[kk][t], dh);
+          dh = mfma32(a2t[m][kk], dlo[kk][t], dh);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float d = dh[r] * gd1[m][t][r];
+          const short hs = bfs(d);
+          sHi[(16 * m + 4 * g + r) * kGP + 16 * t + c] = hs;
+          sLo[(16 * m + 4 * g + r) * kGP + 16 * t + c] =
+              bfs(d - bf2f((uint16_t)hs));
+        }
+      }
+    // ---- weight gradient of layer 1 (rows: 8 features, ones, zeros)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+    {
+      const s16x8 ax = *(const s16x8*)(sX + c * kGP + 8 * g);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const s16x8 bh = *(const s16x8*)(sHi + (16 * b + c) * kGP + 8 * g);
+        const s16x8 bl = *(const s16x8*)(sLo + (16 * b + c) * kGP + 8 * g);
+        gW1[b] = mfma32(ax, bh, gW1[b]);
+        gW1[b] = mfma32(ax, bl, gW1[b]);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
   }
-  float* out = partial + (size_t)blockIdx.x * (kNParams + 1);
-  for (int m = 0; m < kOwn; ++m) {
-    const int p = tid + 64 * m;
-    if (p < kNParams) out[p] = sacc[m][tid];
+
+  // ---- this wavefront's row of per-parameter sums
+  float* out = partial + (size_t)row * (kNParams + 1);
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int k = 4 * g + r, j = 16 * b + c;
+      if (k < kNF) out[kOffW1 + k * kNH + j] = gW1[b][r];
+      if (k == kNF) out[kOffB1 + j] = gW1[b][r];   // the ones row
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+        out[kOffW2 + (16 * a + 4 * g + r) * kNH + j] = gW2[a][b][r];
+    }
+  // per-unit sums over the 16 sample lanes of each lane group
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      float sb = gb2[m][r], sw = gw3[m][r];
+#pragma unroll
+      for (int o = 1; o < 16; o <<= 1) {
+        sb += __shfl_xor(sb, o);
+        sw += __shfl_xor(sw, o);
+      }
+      if (c == 0) {
+        out[kOffB2 + 16 * m + 4 * g + r] = sb;
+        out[kOffW3 + 16 * m + 4 * g + r] = sw;
+      }
+    }
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    gb3 += __shfl_xor(gb3, o);
+    lsum += __shfl_xor(lsum, o);
   }
-  sl[tid] = lsum;
-  __syncthreads();
-  if (tid == 0) {
-    float s = 0.f;
-    for (int b = 0; b < 64; ++b) s += sl[b];
-    out[kNParams] = s;
+  if (l == 0) {
+    out[kOffB3] = gb3;
+    out[kNParams] = lsum;
   }
 }
 
-__global__ __launch_bounds__(256) void k_grad_reduce(const float* __restrict__ partial,
-                                                     int nblocks,
-                                                     float* __restrict__ grad,
-                                                     float* __restrict__ loss) {
-  const int p = blockIdx.x * 256 + threadIdx.x;
-  if (p > kNParams) return;
+// Sum of the partial rows, fixed order: a block takes 64 consecutive
+// entries (coalesced row reads); its eight wavefronts sum rows q, q+8, ...
+// (q = wavefront) and the eight sums are added pairwise in a fixed order.
+// With adam_step > 0 the Adam update (Kingma & Ba 2015) of those
+// parameters follows at once.
+constexpr int kRedWaves = 8;
+__global__ __launch_bounds__(64 * kRedWaves) void k_grad_reduce(
+    const float* __restrict__ partial, int nrows, float* __restrict__ grad,
+    float* __restrict__ loss, float* __restrict__ P, float* __restrict__ m,
+    float* __restrict__ v, int adam_step, float lr, float b1, float b2,
+    float eps) {
+  __shared__ float sh[kRedWaves][64];
+  const int q = (int)threadIdx.x >> 6, j = (int)threadIdx.x & 63;
+  const int p = (int)blockIdx.x * 64 + j;
   float s = 0.f;
-  for (int b = 0; b < nblocks; ++b) s += partial[(size_t)b * (kNParams + 1) + p];
-  if (p < kNParams)
-    grad[p] = s;
-  else
-    loss[0] = s;
-}
-
-// Adam (Kingma & Ba 2015).
-__global__ __launch_bounds__(256) void k_adam(float* __restrict__ P,
-                                              float* __restrict__ m,
-                                              float* __restrict__ v,
-                                              const float* __restrict__ g,
-                                              int step, float lr, float b1,
-                                              float b2, float eps) {
-  const int p = blockIdx.x * 256 + threadIdx.x;
-  if (p >= kNParams) return;
-  const float gi = g[p];
-  const float mi = b1 * m[p] + (1.f - b1) * gi;
-  const float vi = b2 * v[p] + (1.f - b2) * gi * gi;
-  m[p] = mi;
-  v[p] = vi;
-  const float mh = mi / (1.f - powf(b1, (float)step));
-  const float vh = vi / (1.f - powf(b2, (float)step));
-  P[p] -= lr * mh / (sqrtf(vh) + eps);
+  if (p <= kNParams)
+    for (int r = q; r < nrows; r += kRedWaves)
+      s += partial[(size_t)r * (kNParams + 1) + p];
+  sh[q][j] = s;
+  __syncthreads();
+  if (q != 0 || p > kNParams) return;
+  const float gi = ((sh[0][j] + sh[1][j]) + (sh[2][j] + sh[3][j])) +
+                   ((sh[4][j] + sh[5][j]) + (sh[6][j] + sh[7][j]));
+  if (p == kNParams) {
+    loss[0] = gi;
+    return;
+  }
+  grad[p] = gi;
+  if (adam_step > 0) {
+    const float mi = b1 * m[p] + (1.f - b1) * gi;
+    const float vi = b2 * v[p] + (1.f - b2) * gi * gi;
+    m[p] = mi;
+    v[p] = vi;
+    const float mh = mi / (1.f - powf(b1, (float)adam_step));
+    const float vh = vi / (1.f - powf(b2, (float)adam_step));
+    P[p] -= lr * mh / (sqrtf(vh) + eps);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_pack_bf16(const float* __restrict__ P,
@@ -936,27 +1139,40 @@ hipError_t launch_flux_samples_natural(
   return hipGetLastError();
 }
 
-hipError_t launch_mlp_grad(const float* params, const float* X,
-                           const float* t, const float* w, int64_t n,
-                           double wsum, float* partial, int nblocks,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_mlp_grad, dim3(nblocks), dim3(64), 0, s, params, X, t,
-                     w, n, (float)(1.0 / wsum), partial, nblocks);
+// two 32-sample steps per wavefront at least (fewer partial rows to sum)
+int mlp_grad_rows(int64_t n, int max_rows) {
+  int64_t r = (n + 2 * kGS - 1) / (2 * kGS);
+  if (r > max_rows) r = max_rows;
+  return r < 1 ? 1 : (int)r;
+}
+
+hipError_t launch_mlp_grad_mfma(const float* params, const float* X,
+                                const float* t, const float* w, int64_t n,
+                                double wsum, float* partial, int nrows,
+                                hipStream_t s) {
+  const int blocks = (nrows + kGWaves - 1) / kGWaves;
+  hipLaunchKernelGGL(k_mlp_grad_mfma, dim3(blocks), dim3(64 * kGWaves), 0, s,
+                     params, X, t, w, n, (float)(1.0 / wsum), partial, nrows);
   return hipGetLastError();
 }
 
-hipError_t launch_grad_reduce(const float* partial, int nblocks, float* grad,
+hipError_t launch_grad_reduce(const float* partial, int nrows, float* grad,
                               float* loss, hipStream_t s) {
-  hipLaunchKernelGGL(k_grad_reduce, dim3((kNParams + 1 + 255) / 256),
-                     dim3(256), 0, s, partial, nblocks, grad, loss);
+  hipLaunchKernelGGL(k_grad_reduce, dim3((kNParams + 1 + 63) / 64),
+                     dim3(64 * kRedWaves), 0, s, partial, nrows, grad, loss,
+                     (float*)nullptr,
+                     (float*)nullptr, (float*)nullptr, 0, 0.f, 0.f, 0.f, 0.f);
   return hipGetLastError();
 }
 
-hipError_t launch_adam(float* params, float* m, float* v, const float* grad,
-                       int step, float lr, float b1, float b2, float eps,
-                       hipStream_t s) {
-  hipLaunchKernelGGL(k_adam, dim3((kNParams + 255) / 256), dim3(256), 0, s,
-                     params, m, v, grad, step, lr, b1, b2, eps);
+hipError_t launch_grad_reduce_adam(const float* partial, int nrows,
+                                   float* grad, float* loss, float* params,
+                                   float* m, float* v, int step, float lr,
+                                   float b1, float b2, float eps,
+                                   hipStream_t s) {
+  hipLaunchKernelGGL(k_grad_reduce, dim3((kNParams + 1 + 63) / 64),
+                     dim3(64 * kRedWaves), 0, s, partial, nrows, grad, loss,
+                     params, m, v, step, lr, b1, b2, eps);
   return hipGetLastError();
 }
 

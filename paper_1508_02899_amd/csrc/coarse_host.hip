@@ -46,11 +46,6 @@ hipError_t device_sum(const float* w, int64_t n, hipStream_t s, double* out) {
   return hipSuccess;
 }
 
-int nblocks_for(const lattice_mlp_t* M, int64_t n) {
-  int64_t b = (n + 63) / 64;
-  if (b > M->max_blocks) b = M->max_blocks;
-  return b < 1 ? 1 : (int)b;
-}
 
 }  // namespace
 
@@ -211,10 +206,10 @@ int lattice_mlp_grad(lattice_mlp_t* M, const float* X, const float* t,
   double ws = 0.0;
   if (device_sum(w, n, M->stream, &ws) != hipSuccess) return LATTICE_EHIP;
   if (!(ws > 0)) return LATTICE_EINVAL;
-  const int nb = nblocks_for(M, n);
-  if (lat::launch_mlp_grad(M->params, X, t, w, n, ws, M->partial, nb,
-                           M->stream) != hipSuccess ||
-      lat::launch_grad_reduce(M->partial, nb, M->grad, M->loss, M->stream) !=
+  const int nr = lat::mlp_grad_rows(n, M->max_blocks);
+  if (lat::launch_mlp_grad_mfma(M->params, X, t, w, n, ws, M->partial, nr,
+                                M->stream) != hipSuccess ||
+      lat::launch_grad_reduce(M->partial, nr, M->grad, M->loss, M->stream) !=
           hipSuccess)
     return LATTICE_EHIP;
   if (grad && hipMemcpyAsync(grad, M->grad, sizeof(float) * lat::kNParams,
@@ -243,15 +238,14 @@ int lattice_mlp_train(lattice_mlp_t* M, const float* X, const float* t,
   const int64_t nwin = n / batch;  // whole windows of the (shuffled) data
   for (int64_t k = 0; k < steps; ++k) {
     const int64_t off = (k % (nwin > 0 ? nwin : 1)) * batch;
-    const int nb = nblocks_for(M, batch);
-    if (lat::launch_mlp_grad(M->params, X + off * lat::kNF, t + off, w + off,
-                             batch, norm, M->partial, nb,
-                             M->stream) != hipSuccess ||
-        lat::launch_grad_reduce(M->partial, nb, M->grad, M->loss,
-                                M->stream) != hipSuccess ||
-        lat::launch_adam(M->params, M->m, M->v, M->grad, ++M->adam_t,
-                         (float)lr, 0.9f, 0.999f, 1e-8f,
-                         M->stream) != hipSuccess)
+    const int nr = lat::mlp_grad_rows(batch, M->max_blocks);
+    if (lat::launch_mlp_grad_mfma(M->params, X + off * lat::kNF, t + off,
+                                  w + off, batch, norm, M->partial, nr,
+                                  M->stream) != hipSuccess ||
+        lat::launch_grad_reduce_adam(M->partial, nr, M->grad, M->loss,
+                                     M->params, M->m, M->v, ++M->adam_t,
+                                     (float)lr, 0.9f, 0.999f, 1e-8f,
+                                     M->stream) != hipSuccess)
       return LATTICE_EHIP;
   }
   if (mlp_sync_bf16(M) != hipSuccess) return LATTICE_EHIP;

@@ -63,18 +63,24 @@ hipError_t launch_flux_samples_natural(
     const float* f_pred, const float* u, const int32_t* sites, int nsites,
     float* X, float* t, float* w, hipStream_t s);
 
-// Per-block partial gradients of the weighted squared loss over n samples
-// (nblocks rows of kNParams + 1 floats: gradient, then the block's loss sum).
-hipError_t launch_mlp_grad(const float* params, const float* X,
-                           const float* t, const float* w, int64_t n,
-                           double wsum, float* partial, int nblocks,
-                           hipStream_t s);
-// Sum of the partials in block order into grad[kNParams] and loss[0].
-hipError_t launch_grad_reduce(const float* partial, int nblocks, float* grad,
+// Per-wavefront partial sums of the loss gradient (matrix cores): nrows
+// rows of kNParams + 1 floats (gradient, then the row's loss sum), one per
+// wavefront; mlp_grad_rows gives the row count for n samples (at most
+// max_rows).
+int mlp_grad_rows(int64_t n, int max_rows);
+hipError_t launch_mlp_grad_mfma(const float* params, const float* X,
+                                const float* t, const float* w, int64_t n,
+                                double wsum, float* partial, int nrows,
+                                hipStream_t s);
+// Sum of the partial rows in a fixed order into grad[kNParams] and loss[0];
+// the _adam form then applies one Adam step (step >= 1) to params.
+hipError_t launch_grad_reduce_adam(const float* partial, int nrows,
+                                   float* grad, float* loss, float* params,
+                                   float* m, float* v, int step, float lr,
+                                   float b1, float b2, float eps,
+                                   hipStream_t s);
+hipError_t launch_grad_reduce(const float* partial, int nrows, float* grad,
                               float* loss, hipStream_t s);
-hipError_t launch_adam(float* params, float* m, float* v, const float* grad,
-                       int step, float lr, float b1, float b2, float eps,
-                       hipStream_t s);
 // bf16 copies of the weights for the matrix-core forward pass.
 hipError_t launch_pack_bf16(const float* params, uint16_t* wq, hipStream_t s);
 
