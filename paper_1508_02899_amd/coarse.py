@@ -219,6 +219,459 @@ def calibrate_output_scale(fine: Lattice, coarse_spec: LatticeSpec, mlp: Mlp,
     return best, scores
 
 
+def time_steps(spec: LatticeSpec, state, flow_slices, *, dt: float,
+               tau_p: float, kappa: float, warmup: int, steps: int,
+               mlp: Mlp | None = None, St: float = 1.0,
+               line_eps: float = 0.0) -> float:
+    """Milliseconds per step of one lattice_step call of ``steps`` steps
+    (after ``warmup`` untimed ones) continuing ``state`` in place, a new
+    flow slice per step (flow_slices [>= warmup + steps, dim, ny, nx]);
+    with ``mlp`` the learned correction at face threshold line_eps."""
+    torch = _torch()
+    lat = Lattice(replace(spec, u_hold=1))
+    if mlp is not None:
+        mlp.attach(lat, St, line_eps)
+    if warmup:
+        lat.step(state, flow_slices[:warmup], tau_p, kappa, dt, warmup)
+    lat.sync()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    lat.step(state, flow_slices[warmup:warmup + steps], tau_p, kappa, dt,
+             steps)
+    e1.record()
+    torch.cuda.synchronize()
+    lat.sync()
+    lat.close()
+    return e0.elapsed_time(e1) / steps
+
+
+def _shifted(flow, k0: int):
+    """The flow callable k -> slice k0 + k, with .all from slice k0."""
+    u = flow.all[k0:]
+    fn = lambda k: u[k:k + 1]  # noqa: E731
+    fn.all = u
+    return fn
+
+
+def fine_reference(fine_spec: LatticeSpec, coarse_spec: LatticeSpec,
+                   f0_fine, flow, checkpoints, *, dt: float, tau_p: float,
+                   kappa: float, levels: int):
+    """Run the fine lattice from a copy of f0_fine under flow.all (one slice
+    per step) and record, at each checkpoint step, the velocity variance and
+    <rho_r^2> of its restriction as the coarse lattice sees them.  Returns
+    (Track of the restricted fine state, restricted initial state, final
+    fine state)."""
+    fine = Lattice(replace(fine_spec, u_hold=1))
+    view = Lattice(replace(coarse_spec, u_hold=1))
+    dim = fine_spec.dim
+    f = f0_fine.clone()
+    T, n = Track(), 0
+    for c in checkpoints:
+        fine.step(f, flow.all[n:c], tau_p, kappa, dt, c - n)
+        n = c
+        observe(view, restrict(f, dim), dt, levels, T, n)
+    fine.sync()
+    g0 = restrict(f0_fine, dim)
+    fine.close()
+    view.close()
+    return T, g0, f
+
+
+def rollout(lat: Lattice, g0, flow, checkpoints, *, dt: float, tau_p: float,
+            kappa: float, levels: int, work=None) -> Track:
+    """Run the coarse lattice ``lat`` (u_hold 1; its network, if attached,
+    as it stands) from g0 under flow.all, recording variance and
+    <rho_r^2> at each checkpoint step; ``work`` (shape of g0) holds the
+    state if given, else a copy is made."""
+    g = g0.clone() if work is None else work.copy_(g0)
+    T, n = Track(), 0
+    for c in checkpoints:
+        lat.step(g, flow.all[n:c], tau_p, kappa, dt, c - n)
+        n = c
+        observe(lat, g, dt, levels, T, n)
+    return T
+
+
+def rollout_loss(track: Track, ref: Track, dx: float, from_step: int):
+    """Mean squared relative velocity-variance error plus the mean squared
+    distance-averaged <rho_r^2> error (Sec. 4.2.1) of a run against the
+    reference track, over the recorded steps >= from_step."""
+    import numpy as np
+    from .lattice import rho_r2_error
+    sel = [i for i, s in enumerate(ref.steps) if s >= from_step]
+    ev = [(track.variance[i] / ref.variance[i] - 1.0) ** 2 for i in sel]
+    er = [rho_r2_error(track.rho_r2[i], ref.rho_r2[i], dx) ** 2 for i in sel]
+    return float(np.mean(ev) + np.mean(er))
+
+
+# packed parameter layout: W1[8][64], b1[64], W2[64][64], b2[64], w3[64], b3
+_OFF_B2, _OFF_W3, _OFF_B3, _NPARAMS = 4672, 4736, 4800, 4801
+
+
+def train_a_posteriori(mlp: Mlp, coarse_spec: LatticeSpec, St: float,
+                       line_eps: float, runs, *, dt: float, tau_p: float,
+                       kappa: float, levels: int, from_step: int,
+                       iters: int = 40, pairs: int = 8, sigma: float = 0.05,
+                       lr: float = 0.04, patience: int = 8, seed: int = 0,
+                       log=None):
+    """A-posteriori (unrolled) training of the network's last layers (b2,
+    w3, b3) on whole coarse runs: ``runs`` lists (ref, g0, flow) triples,
+    and the loss is the mean over them of rollout_loss of the coarse
+    lattice with the network attached, run from g0 under flow against the
+    restricted fine run ref (see fine_reference), so the network is judged
+    on the states its own corrections produce, over every step of each
+    run.  The run has no adjoint here, so the gradient is estimated by
+    evolution strategies: ``pairs`` antithetic Gaussian perturbations of
+    relative size sigma per iteration (each a complete set of runs),
+    centred-rank fitness shaping and an Adam step whose size falls from lr
+    to lr/10 along a half cosine, all in units of each parameter group's
+    RMS.  The search stops early once ``patience`` iterations in a row
+    have not lowered the lowest loss seen; those parameters are written
+    into mlp.  Host arithmetic touches only these 129 numbers.  Returns
+    (loss before, loss after, per-iteration losses)."""
+    import numpy as np
+    torch = _torch()
+    rng = np.random.default_rng(seed)
+    P0 = np.asarray(mlp.get_params(), dtype=np.float64)
+    tail = slice(_OFF_B2, _NPARAMS)
+    th0 = P0[tail].copy()
+
+    def rms(v):
+        return float(np.sqrt(np.mean(v * v)))
+
+    w3s = max(rms(P0[_OFF_W3:_OFF_B3]), 1e-4)
+    S = np.empty_like(th0)
+    S[:_OFF_W3 - _OFF_B2] = max(rms(P0[_OFF_B2:_OFF_W3]), 1e-2)
+    S[_OFF_W3 - _OFF_B2:] = w3s
+    lat = Lattice(replace(coarse_spec, u_hold=1))
+    mlp.attach(lat, St, line_eps)
+    work = torch.empty_like(runs[0][1])
+
+    def loss_at(z):
+        P = P0.copy()
+        P[tail] = th0 + S * z
+        mlp.set_params(P.astype(np.float32))
+        total = 0.0
+        for ref, g0, flow in runs:
+            T = rollout(lat, g0, flow, ref.steps, dt=dt, tau_p=tau_p,
+                        kappa=kappa, levels=levels, work=work)
+            total += rollout_loss(T, ref, coarse_spec.dx, from_step)
+        return total / len(runs)
+
+    z = np.zeros_like(th0)
+    m = np.zeros_like(z)
+    v = np.zeros_like(z)
+    first = best = loss_at(z)
+    zbest, since = z.copy(), 0
+    hist = [first]
+    for it in range(1, iters + 1):
+        eps = rng.standard_normal((pairs, z.size))
+        lp = np.array([loss_at(z + sigma * e) for e in eps])
+        lm = np.array([loss_at(z - sigma * e) for e in eps])
+        ranks = np.empty(2 * pairs)
+        ranks[np.argsort(np.concatenate([lp, lm]))] = np.arange(2 * pairs)
+        ranks = ranks / (2 * pairs - 1) - 0.5
+        g = ((ranks[:pairs] - ranks[pairs:])[:, None] * eps).sum(0) / (
+            pairs * sigma)
+        m = 0.9 * m + 0.1 * g
+        v = 0.999 * v + 0.001 * g * g
+        step = lr * (0.1 + 0.45 * (1 + math.cos(math.pi * (it - 1) / iters)))
+        z = z - step * (m / (1 - 0.9 ** it)) / (
+            np.sqrt(v / (1 - 0.999 ** it)) + 1e-8)
+        cur = loss_at(z)
+        hist.append(cur)
+        if cur < best:
+            best, zbest, since = cur, z.copy(), 0
+        else:
+            since += 1
+        if log is not None:
+            log(f"a-posteriori iteration {it}: loss {cur:.4e} (best "
+                f"{best:.4e}, start {first:.4e})")
+        if since >= patience:
+            break
+    P = P0.copy()
+    P[tail] = th0 + S * zbest
+    mlp.set_params(P.astype(np.float32))
+    mlp.attach(lat, St, line_eps)
+    lat.sync()
+    lat.close()
+    return first, best, hist
+
+
+def select_on_validation(fine_spec: LatticeSpec, coarse_spec: LatticeSpec,
+                         mlp: Mlp, St: float, f0_fine, flow, *, steps: int,
+                         dt: float, tau_p: float, kappa: float, thresholds,
+                         scales, min_speedup: float, from_step: int = 50,
+                         every: int = 25, time_warmup: int = 5,
+                         time_steps_n: int = 20):
+    """Choose the face threshold and the output scale of a trained network
+    on a validation flow (distinct from the training and the evaluation
+    flows): every (threshold, scale) pair runs the coarse lattice from the
+    restricted f0_fine under ``flow`` for ``steps`` steps, against the
+    restricted fine run; each threshold's step time is measured against the
+    fine lattice's on the final states.  Among the pairs whose speed-up
+    reaches min_speedup, the one with the smallest max(mean variance error,
+    mean <rho_r^2> error) wins; if none reaches it, the best pair of the
+    fastest threshold.  The chosen scale is folded into the output layer of
+    ``mlp``.  Returns (threshold, scale, {(threshold, scale): (variance
+    error, <rho_r^2> error)}, {threshold: speed-up})."""
+    import numpy as np
+    torch = _torch()
+    levels = int(math.log2(min(coarse_spec.nx, coarse_spec.ny))) + 1
+    checkpoints = list(range(every, steps + 1, every))
+    ref, g0, ff = fine_reference(fine_spec, coarse_spec, f0_fine, flow,
+                                 checkpoints, dt=dt, tau_p=tau_p,
+                                 kappa=kappa, levels=levels)
+    P0 = np.asarray(mlp.get_params(), dtype=np.float32)
+    lat = Lattice(replace(coarse_spec, u_hold=1))
+    work = torch.empty_like(g0)
+    table, finals = {}, {}
+    for c in scales:
+        P = P0.copy()
+        P[_OFF_W3:] *= c          # w3 and b3
+        mlp.set_params(P)
+        for eps in thresholds:
+            mlp.attach(lat, St, eps)
+            T = rollout(lat, g0, flow, checkpoints, dt=dt, tau_p=tau_p,
+                        kappa=kappa, levels=levels, work=work)
+            e = errors({"ref": ref, "run": T}, "ref", coarse_spec.dx,
+                       from_step=from_step)["run"]
+            table[(eps, c)] = (e["variance"], e["rho_r2"])
+            if c == scales[0]:
+                finals[eps] = work.clone()
+    lat.sync()
+    lat.close()
+    extra = flow.all[steps:steps + time_warmup + time_steps_n]
+    if extra.shape[0] < time_warmup + time_steps_n:
+        extra = flow.all[:time_warmup + time_steps_n]
+    ms_fine = time_steps(fine_spec, ff, extra, dt=dt, tau_p=tau_p,
+                         kappa=kappa, warmup=time_warmup,
+                         steps=time_steps_n)
+    mlp.set_params(P0)
+    speed = {}
+    for eps in thresholds:
+        ms = time_steps(coarse_spec, finals[eps], extra, dt=dt, tau_p=tau_p,
+                        kappa=kappa, warmup=time_warmup, steps=time_steps_n,
+                        mlp=mlp, St=St, line_eps=eps)
+        speed[eps] = ms_fine / ms
+    ok = [k for k in table if speed[k[0]] >= min_speedup]
+    if ok:
+        best = min(ok, key=lambda k: max(table[k]))
+    else:
+        fast = max(thresholds, key=lambda e: speed[e])
+        best = min([k for k in table if k[0] == fast],
+                   key=lambda k: max(table[k]))
+    P = P0.copy()
+    P[_OFF_W3:] *= best[1]
+    mlp.set_params(P)
+    return best[0], best[1], table, speed
+
+
+def workload_flows(n: int, nv_fine: int, vmax: float, lengths: dict,
+                   seeds: dict | None = None):
+    """The three distinct synthetic flows of the coarse-model workflow on an
+    n^2 periodic lattice (the 32-mode streamfunction flow with tau_f = 1,
+    sampled every step dt of the fine lattice, nv_fine velocities up to
+    Vmax = vmax u_rms): ``lengths`` maps "train", "valid", "eval" to their
+    slice counts.  Each is a callable k -> slice [1, 2, n, n] (device) with
+    the slices stacked in .all."""
+    torch = _torch()
+    from . import inputs
+    if seeds is None:
+        seeds = {"train": inputs.seed_for(5, 1), "valid": inputs.seed_for(5, 3),
+                 "eval": inputs.seed_for(5, 2)}
+    L = 2 * math.pi
+    dt = (L / n) / (vmax / ((nv_fine - 1) // 2))
+    out = {}
+    for k, nsl in lengths.items():
+        u = torch.from_numpy(inputs.flow2d_streamfunction(
+            n, L, nsl, kmax=32, tau_f=1.0, dt=dt, seed=seeds[k])).cuda()
+        fn = (lambda uu: (lambda j: uu[j:j + 1]))(u)
+        fn.all = u
+        out[k] = fn
+    return out
+
+
+def build_and_evaluate(n: int, nv_fine: int, St: float, kappa: float,
+                       vmax: float, flows: dict, *, spin: int = 60,
+                       train_steps: int = 200, sites_per_step: int = 2048,
+                       lrs=(3e-3, 1e-3, 3e-4), adam_steps: int = 27000,
+                       train_eps: float = 8e-3, es_eps: float = 1.8e-2,
+                       es_steps: int = 200, es_every: int = 25,
+                       es_offsets=(0, 200), es_iters: int = 40,
+                       es_pairs: int = 8,
+                       thresholds=(8e-3, 1.2e-2, 1.8e-2, 2.4e-2, 3.2e-2,
+                                   4.8e-2, 6.4e-2),
+                       scales=(0.8, 1.0, 1.25), min_speedup: float = 4.1,
+                       target_speedup: float = 4.0,
+                       val_steps: int = 200, eval_steps: int = 200,
+                       from_step: int = 50, every: int = 25,
+                       time_warmup: int = 5, time_n: int = 20,
+                       all_faces: bool = False, seed: int = 5, log=None):
+    """The whole coarse-model workflow for one Stokes number on an n^2
+    periodic lattice (fine nv_fine^2 velocities, Vmax = vmax u_rms, dt the
+    fine lattice's CFL-1 streaming step, tau_p = St L / u_rms), with three
+    distinct flows (``flows``: "train", "valid", "eval"; callables
+    k -> slice [1, 2, n, n] with the slices stacked in .all):
+
+    1. a-priori training on least-norm targets from a fine run under the
+       training flow (faces below train_eps of the site mass dropped);
+    2. a-posteriori training of the last layers on whole coarse runs
+       against the restricted fine runs, from the initial state under the
+       training flow from each of its slices es_offsets
+       (train_a_posteriori, face threshold es_eps);
+    3. the face threshold (training keeps every face the network will see:
+       train_eps <= every threshold) and the output scale chosen on the
+       validation flow under the speed-up constraint min_speedup
+       (select_on_validation; above the target_speedup that the held-out
+       run is judged by, so that the few per cent by which step times vary
+       between runs do not decide the outcome);
+    4. evaluation under the held-out flow: fine, plain coarse and corrected
+       coarse side by side from the same initial state, errors against both
+       the restricted fine state and the fine state, and per-step times of
+       each lattice (one lattice_step call of time_n steps continuing the
+       evaluated states, a new flow slice per step).
+
+    Returns a dict of the settings chosen and the measurements."""
+    import time
+    import numpy as np
+    torch = _torch()
+    from . import inputs
+    if not all(train_eps <= e for e in thresholds) or train_eps > es_eps:
+        raise ValueError("train_eps must not exceed any face threshold")
+    L = 2 * math.pi
+    dx = L / n
+    dv = vmax / ((nv_fine - 1) // 2)
+    dt = dx / dv
+    tau_p = St * L
+    say = log or (lambda *_: None)
+    need = {"train": max(spin + train_steps, max(es_offsets) + es_steps),
+            "valid": val_steps + 25, "eval": eval_steps}
+    for k, m in need.items():
+        if flows[k].all.shape[0] < m:
+            raise ValueError(f"the {k} flow needs {m} slices")
+    fs = LatticeSpec(dim=2, nx=n, ny=n, nv=nv_fine, dx=dx)
+    everything = [fl.all for fl in flows.values()]
+    nsf = max(nsub_for(fs, u, tau_p, kappa, dt) for u in everything)
+    fs = replace(fs, nsub=nsf)
+    cs = coarse_spec(fs)
+    nsc = max(nsub_for(cs, u, tau_p, kappa, dt) for u in everything)
+    cs = coarse_spec(fs, nsc)
+    levels = int(math.log2(n)) + 1
+    say(f"St {St}: fine nsub {nsf}, coarse nsub {nsc}")
+
+    def ic():
+        return torch.from_numpy(inputs.gaussian_ic(2, n, nv_fine, dx, dv,
+                                                   ny=n)).cuda()
+
+    out = {"St": St, "nsub_fine": nsf, "nsub_coarse": nsc}
+    # 1. a priori
+    fine, coarse, mlp = Lattice(fs), Lattice(cs), Mlp()
+    mlp.set_params(initial_params(seed))
+    f = ic()
+    ftr = flows["train"]
+    for k in range(spin):
+        fine.step(f, ftr(k), tau_p, kappa, dt, 1)
+    X, t, w = collect_samples(fine, coarse, mlp, f, ftr, steps=train_steps,
+                              dt=dt, tau_p=tau_p, kappa=kappa, St=St,
+                              sites_per_step=sites_per_step, seed=1,
+                              first_step=spin, rel_eps=train_eps)
+    fine.close()
+    coarse.close()
+    del f
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for lr in lrs:
+        loss = mlp.train(X, t, w, batch=8192, steps=adam_steps, lr=lr)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    out["a_priori"] = {"samples": int(t.numel()), "train_eps": train_eps,
+                       "adam_steps": adam_steps * len(lrs), "batch": 8192,
+                       "seconds": round(t_train, 3),
+                       "last_minibatch_loss": loss}
+    del X, t, w
+    say(f"St {St}: a-priori training done, last minibatch loss {loss:.3e}")
+    # 2. a posteriori, on the training flow from a fresh state
+    t0 = time.perf_counter()
+    cps = list(range(es_every, es_steps + 1, es_every))
+    runs = []
+    for k0 in es_offsets:
+        fl = _shifted(ftr, k0)
+        ref, g0, _ = fine_reference(fs, cs, ic(), fl, cps, dt=dt,
+                                    tau_p=tau_p, kappa=kappa, levels=levels)
+        runs.append((ref, g0, fl))
+    l0, l1, hist = train_a_posteriori(mlp, cs, St, es_eps, runs, dt=dt,
+                                      tau_p=tau_p, kappa=kappa,
+                                      levels=levels, from_step=from_step,
+                                      iters=es_iters, pairs=es_pairs,
+                                      seed=seed, log=say)
+    del runs
+    out["a_posteriori"] = {"loss_before": l0, "loss_after": l1,
+                           "iterations": len(hist) - 1, "pairs": es_pairs,
+                           "face_threshold": es_eps,
+                           "training_runs": len(es_offsets),
+                           "rollouts": len(es_offsets) *
+                           (1 + (len(hist) - 1) * (2 * es_pairs + 1)),
+                           "seconds": round(time.perf_counter() - t0, 3)}
+    say(f"St {St}: a-posteriori loss {l0:.4e} -> {l1:.4e}")
+    # 3. threshold and scale on the validation flow
+    eps, scale, table, speed = select_on_validation(
+        fs, cs, mlp, St, ic(), flows["valid"], steps=val_steps, dt=dt,
+        tau_p=tau_p, kappa=kappa, thresholds=thresholds, scales=scales,
+        min_speedup=min_speedup, from_step=from_step, every=every,
+        time_warmup=5, time_steps_n=20)
+    out["validation"] = {
+        "face_threshold": eps, "output_scale": scale,
+        "min_speedup": min_speedup,
+        "errors": {f"{k[0]:g}|{k[1]:g}": [round(v[0], 5), round(v[1], 6)]
+                   for k, v in table.items()},
+        "speedup": {f"{k:g}": round(v, 3) for k, v in speed.items()}}
+    say(f"St {St}: chosen face threshold {eps:g}, output scale {scale:g} "
+        f"(validation {table[(eps, scale)]}, speed-up {speed[eps]:.2f})")
+    # 4. held-out evaluation
+    fine, plain, corr = Lattice(fs), Lattice(cs), Lattice(cs)
+    mlp.attach(corr, St, eps)
+    fev = flows["eval"]
+    tracks, ff, states = compare(fine, {"plain": plain, "mlp": corr}, ic(),
+                                 fev, steps=eval_steps, dt=dt, tau_p=tau_p,
+                                 kappa=kappa, levels=levels, every=every)
+    err_r = errors({k: v for k, v in tracks.items() if k != "fine"},
+                   "fine_R", dx, from_step=from_step)
+    err_f = errors(tracks, "fine", dx, from_step=from_step)
+    m0 = plain.moments(states["plain"], dt)["mass"]
+    m1 = corr.moments(states["mlp"], dt)["mass"]
+    out["mass_rel_diff"] = abs(m1 - m0) / m0
+    out["min_value"] = float(states["mlp"].min())
+    for lat in (fine, plain, corr):
+        lat.close()
+    sl = fev.all[eval_steps:eval_steps + time_warmup + time_n]
+    if sl.shape[0] < time_warmup + time_n:
+        sl = fev.all[:time_warmup + time_n]
+    kw = dict(dt=dt, tau_p=tau_p, kappa=kappa, warmup=time_warmup,
+              steps=time_n)
+    ms_fine = time_steps(fs, ff, sl, **kw)
+    ms_plain = time_steps(cs, states["plain"], sl, **kw)
+    ms_mlp = time_steps(cs, states["mlp"], sl, mlp=mlp, St=St, line_eps=eps,
+                        **kw)
+    if all_faces:
+        out["ms_per_step_coarse_all_faces"] = time_steps(
+            cs, states["plain"].clone(), sl, mlp=mlp, St=St, line_eps=0.0,
+            **kw)
+    mlp.close()
+    out.update(ms_per_step_fine=ms_fine, ms_per_step_coarse_plain=ms_plain,
+               ms_per_step_coarse_mlp=ms_mlp,
+               speedup_vs_fine=ms_fine / ms_mlp,
+               errors_vs_restricted_fine=err_r, errors_vs_fine=err_f)
+    e = err_r["mlp"]
+    out["meets_target"] = bool(out["speedup_vs_fine"] >= target_speedup and
+                               e["variance"] <= 0.02 and e["rho_r2"] <= 0.02)
+    say(f"St {St}: held-out speed-up {out['speedup_vs_fine']:.2f}, variance "
+        f"error {e['variance']:.4f}, <rho_r^2> error {e['rho_r2']:.5f}")
+    return out
+
+
 def errors(tracks: dict, ref: str, dx: float, from_step: int = 0):
     """Per run: mean relative error of the velocity variance and the mean
     distance-averaged relative error of <rho_r^2> against the reference
