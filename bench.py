@@ -65,6 +65,9 @@ WORKLOADS = {
 KERNEL_SOURCES = {
     2: ["paper_1508_02899_amd/csrc/step2d.h",
         "paper_1508_02899_amd/csrc/device_common.h"],
+    "batch": ["paper_1508_02899_amd/csrc/batch1d.hip",
+              "paper_1508_02899_amd/csrc/parts1d.h",
+              "paper_1508_02899_amd/csrc/device_common.h"],
     1: ["paper_1508_02899_amd/csrc/step1d.hip",
         "paper_1508_02899_amd/csrc/step1d_parts.hip",
         "paper_1508_02899_amd/csrc/parts1d.h",
@@ -200,19 +203,29 @@ def cpu_sample(w, dx, dv, dt, tau_p):
             "seconds": round(el, 3)}
 
 
-def batch_members(count, nsteps):
+def batch_shapes(count):
+    """(nx, nv, St) of the members of the batched workload: nx uniform in
+    [512, 8192], nv in {33, 65, 129}, St log-uniform in [0.1, 10]."""
     import numpy as np
 
-    from paper_1508_02899_amd import Member, inputs
+    from paper_1508_02899_amd import inputs
     rng = np.random.default_rng(inputs.seed_for(4))
+    out = []
+    for _ in range(count):
+        nx = int(rng.integers(512, 8193))
+        nv = int(rng.choice([33, 65, 129]))
+        St = float(10 ** rng.uniform(-1, 1))
+        out.append((nx, nv, St))
+    return out
+
+
+def batch_members(count, nsteps):
+    from paper_1508_02899_amd import Member, inputs
     L = 2 * math.pi
     mems, states, flows = [], [], []
     hold = 50
     nsl = (nsteps + hold - 1) // hold
-    for r in range(count):
-        nx = int(rng.integers(512, 8193))
-        nv = int(rng.choice([33, 65, 129]))
-        St = float(10 ** rng.uniform(-1, 1))
+    for r, (nx, nv, St) in enumerate(batch_shapes(count)):
         tau_p = St * L
         vmax = inputs.choose_vmax(nx, L, nv, tau_p, 4.0)
         dv = vmax / ((nv - 1) // 2)
@@ -280,9 +293,26 @@ def bench_batch(args, w):
     b.sync()
     ms = ev0.elapsed_time(ev1)
     cells = b.total_cells
+    if args.copy_calibration:
+        # the plain copy kernel on cells // 3 * 3 values (a 1D lattice of
+        # nv 3): a known-size reference for the HBM byte counters
+        from paper_1508_02899_amd import Lattice, LatticeSpec
+        cl = Lattice(LatticeSpec(dim=1, nx=cells // 3, nv=3, dx=1.0))
+        g = torch.empty((3, cells // 3), dtype=torch.float32, device="cuda")
+        g2 = torch.empty_like(g)
+        for _ in range(args.copy_calibration):
+            cl.copy_state(g2, g)
+        cl.sync()
+        cl.close()
+        del g, g2
     value = cells * K / (ms / 1e3) / 1e9
     sched_text = ("resident schedule (one launch per call, per-member step "
                   "barriers)" if resident else f"graph of {G} steps")
+    traffic = None
+    if resident and not w.get("st_set"):
+        per_step = load_traffic(args.workload, "batch")
+        if per_step is not None:  # HBM bytes per launch of K steps
+            traffic = round(per_step * K)
     drift = float(np.max(np.abs(m1[:, 0] - m0[:, 0]) / m0[:, 0]))
     achieved = (2 * cells * 4 + b.total_u * 4 / max(1, K)) * K / (ms / 1e3) / 1e9
     out = {
@@ -309,7 +339,7 @@ def bench_batch(args, w):
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None,
+                     "traffic": traffic,
                      "kernel": ("k_batch_resident" if resident else
                                 "k_batch1d (all classes)")},
     }
@@ -413,15 +443,20 @@ def bench_coarse(args, w):
     print(json.dumps(out), flush=True)
 
 
-def load_traffic(name):
+def load_traffic(name, key=None):
+    """HBM bytes per launch (per step for the batched workload) recorded
+    under profiles/, if the kernel sources still hash to the recorded
+    value."""
     path = os.path.join(ROOT, "profiles", f"traffic_{name}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         t = json.load(fh)
-    if t.get("kernel_hash") != kernel_hash(WORKLOADS[name]["dim"]):
+    if key is None:
+        key = WORKLOADS[name]["dim"]
+    if t.get("kernel_hash") != kernel_hash(key):
         return None  # counters were taken on another version of the kernel
-    return t.get("bytes_per_launch")
+    return t.get("bytes_per_step" if key == "batch" else "bytes_per_launch")
 
 
 def _rocpd(folder):
@@ -480,6 +515,72 @@ def summarize_trace(args):
     print(path)
 
 
+def summarize_batch(args):
+    """Kernel-time and HBM-byte summaries of the batched workload under the
+    resident schedule: the FETCH_SIZE / WRITE_SIZE of its largest
+    k_batch_resident dispatch (the timed call of --steps steps), scaled by
+    the plain copy kernel of the same run (cells // 3 * 3 values each way),
+    against the algorithmic bytes of those steps (state read and written
+    once per step, one flow value per site)."""
+    import statistics
+    w = WORKLOADS[args.workload]
+    K = args.steps
+    trace, fetch, write = (_rocpd(d) for d in args.summarize)
+    kern = "k_batch_resident"
+    shapes = batch_shapes(w["batch"])
+    cells = sum(nx * nv for nx, nv, _ in shapes)
+    sites = sum(nx for nx, _, _ in shapes)
+    per_step = 2 * cells * 4 + sites * 4
+    copy = cells // 3 * 3 * 4
+    cmd = args.command or "(command not recorded)"
+    top, lines = _trace_table(trace, args.workload, cmd)
+    name = f"{kern}_{args.workload}"
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", f"{name}_kernel_stats.md"),
+              "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    f_k = max(_counter(fetch, "FETCH_SIZE", f"%{kern}%"))
+    w_k = max(_counter(write, "WRITE_SIZE", f"%{kern}%"))
+    f_c = statistics.median(_counter(fetch, "FETCH_SIZE", "%k_copy16%"))
+    w_c = statistics.median(_counter(write, "WRITE_SIZE", "%k_copy16%"))
+    ff, fw = copy / 1024.0 / f_c, copy / 1024.0 / w_c
+    traffic = (f_k * ff + w_k * fw) * 1024.0
+    out = {"workload": args.workload, "kernel": kern,
+           "kernel_hash": kernel_hash("batch"), "steps_per_launch": K,
+           "bytes_per_launch": round(traffic),
+           "bytes_per_step": round(traffic / K),
+           "read_bytes": round(f_k * ff * 1024.0),
+           "write_bytes": round(w_k * fw * 1024.0),
+           "algorithmic_bytes_per_step": per_step,
+           "traffic_over_algorithmic": round(traffic / K / per_step, 5),
+           "fetch_kib_per_dispatch": f_k, "write_kib_per_dispatch": w_k,
+           "copy_fetch_kib": f_c, "copy_write_kib": w_c,
+           "copy_bytes_each_way": copy,
+           "fetch_scale": round(ff, 5), "write_scale": round(fw, 5),
+           "command": cmd}
+    with open(os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json"),
+              "w") as fh:
+        json.dump(out, fh, indent=1)
+        fh.write("\n")
+    md = [f"# HBM bytes of {kern}: {args.workload}", "",
+          "FETCH_SIZE and WRITE_SIZE are read in separate rocprofv3 --pmc "
+          "runs of the command below (one counter each); the value is that "
+          f"of the largest {kern} dispatch (the timed call of {K} steps).  "
+          "Scale: the plain copy kernel k_copy16 in the same run moves "
+          f"exactly {copy} B each way.", "", "    " + cmd, "",
+          "| | FETCH_SIZE KiB | WRITE_SIZE KiB |", "|---|---|---|",
+          f"| {kern} ({K} steps) | {f_k:.1f} | {w_k:.1f} |",
+          f"| k_copy16 | {f_c:.1f} | {w_c:.1f} |",
+          f"| scale (known / counted) | {ff:.4f} | {fw:.4f} |", "",
+          f"HBM traffic per step: {traffic / K:.4g} B (read "
+          f"{f_k * ff * 1024 / K:.4g}, write {w_k * fw * 1024 / K:.4g}); "
+          f"algorithmic {per_step} B; ratio {traffic / K / per_step:.4f}."]
+    with open(os.path.join(ROOT, "profiles", f"{name}_hbm_bytes.md"),
+              "w") as fh:
+        fh.write("\n".join(md) + "\n")
+    print(json.dumps(out))
+
+
 def summarize(args):
     """Write the kernel-time and HBM-byte summaries of one workload under
     profiles/ from rocprofv3 output folders.  HBM bytes: the FETCH_SIZE and
@@ -488,6 +589,8 @@ def summarize(args):
     kernel (k_copy16: reads and writes exactly one state) in the same run."""
     import statistics
     w = WORKLOADS[args.workload]
+    if w.get("batch") and not w.get("st_set"):
+        return summarize_batch(args)
     trace, fetch, write = (_rocpd(d) for d in args.summarize)
     kern = step_kernel(w["dim"], w["n"], w["nv"], w["dtype"])
     elem = 8 if w["dtype"] == "f64" else 4

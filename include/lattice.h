@@ -59,7 +59,8 @@ enum {
   LATTICE_ENOMEM = -5,     /* device allocation failed */
   LATTICE_ENONFINITE = -6, /* moments are NaN or Inf */
   LATTICE_ENOTSUP = -7,    /* valid but not compiled in (2D nv, see below) */
-  LATTICE_ETOOBIG = -8     /* state too large for lattice_step_noalloc */
+  LATTICE_ETOOBIG = -8,    /* state too large for lattice_step_noalloc */
+  LATTICE_ETIMEOUT = -9    /* a resident batched launch gave up waiting */
 };
 
 /*
@@ -345,11 +346,14 @@ const char* lattice_last_error(const lattice_t* L);
  * Offsets are assigned by lattice_batch_init in member order (query them
  * with lattice_batch_layout).
  *
- * One lattice_batch_step call queues, per time step, one persistent kernel
- * per velocity-capacity class (members with nv <= 9, 17, 33, 65, 129); the
+ * Two schedules (lattice_batch_schedule).  Per step (the default): one
+ * lattice_batch_step call queues, per time step, one persistent kernel per
+ * velocity-capacity class (members with nv <= 9, 17, 33, 65, 129); the
  * classes run on parallel streams (they touch disjoint memory).  With
  * use_graph != 0 the per-step launches are captured once into a HIP graph
- * of graph_steps steps and replayed.
+ * of graph_steps steps and replayed.  Resident: one kernel advances every
+ * member by all the steps of the call, with a per-member step barrier on
+ * device counters instead of a launch boundary per step.
  * ===================================================================== */
 typedef struct lattice_batch lattice_batch_t;
 
@@ -391,6 +395,41 @@ int lattice_batch_layout(const lattice_batch_t* B, int64_t* f_off,
 int lattice_batch_tune(lattice_batch_t* B, int32_t cap, int32_t block,
                        int32_t grid_per_cu);
 
+enum { LATTICE_BATCH_PER_STEP = 0, LATTICE_BATCH_RESIDENT = 1 };
+
+/* Schedule of lattice_batch_step.  LATTICE_BATCH_PER_STEP (default): as
+ * described above.  LATTICE_BATCH_RESIDENT: each call is one launch (per
+ * 2^31 work items) of a kernel that advances every member by all the
+ * steps.  The members are split among the chip's XCDs (balanced by cells;
+ * each XCD is one L2 cache domain), and all the tiles of a member, at
+ * every step, are updated on its XCD: workgroups take chunks of `chunk`
+ * (step, tile) items from their XCD's device work counter, in step order
+ * (the tiles of one step member by member; split-column tiles, 128 sites
+ * for nv 17, 33, 65 and 64 for nv 129).  A member's tile of step t > 0
+ * starts once the member's device counter of finished tiles shows all of
+ * its step t-1 tiles done (they wrote what the pull streaming of step t
+ * reads, and have read the buffer that step t writes): a barrier per
+ * member, none across the grid, so members of different sizes and
+ * velocity lattices overlap.  Finished tiles are published through the
+ * shared L2 of the XCD (stores complete before the count; the reader's L1
+ * dropped before loading).  A workgroup publishes its finished tiles
+ * before it waits and only waits on items taken before its own, so the
+ * queues drain whatever the residency; a launch that leaves items of some
+ * XCD untaken (no workgroup ran there) is reported like a time-out.
+ * Every member's nv must be 17, 33, 65 or 129 (else ENOTSUP; the schedule
+ * is unchanged); use_graph and graph_steps of lattice_batch_step are then
+ * ignored, and the per-class decompositions of lattice_batch_tune are not
+ * used.  grid_per_cu: resident workgroups per compute unit (1..16, 0 = as
+ * many as fit); chunk: items per counter fetch (1..64, 0 = 4).
+ * wait_limit: polls (each about a microsecond) after which a waiting
+ * workgroup gives up; the launch then ends early, the state is undefined
+ * and lattice_batch_sync returns ETIMEOUT; 0 = 2^22; a negative value makes
+ * every wait give up at once (to exercise that path).  EINVAL, ENOTSUP,
+ * EHIP. */
+int lattice_batch_schedule(lattice_batch_t* B, int32_t mode,
+                           int32_t grid_per_cu, int32_t chunk,
+                           int64_t wait_limit);
+
 /* Advance every member by nsteps (asynchronous).  u must hold, for each
  * member, ceil(nsteps/u_hold) slices (1 if u_hold == 0).  The drift CFL of
  * Eq. 3 is checked on the device per member; a violating member is frozen
@@ -406,9 +445,10 @@ int lattice_batch_step(lattice_batch_t* B, float* f, const float* u,
  * order.  Synchronous.  EINVAL, EHIP. */
 int lattice_batch_moments(lattice_batch_t* B, const float* f, double* out);
 
-/* Wait; return ECFL if some member was frozen since the last report (its
- * flag is copied to member_flags[count] when that is not NULL, and
- * cleared), else 0 / EHIP. */
+/* Wait; return ETIMEOUT if a resident launch gave up waiting since the
+ * last report (cleared), else ECFL if some member was frozen since the last
+ * report (its flag is copied to member_flags[count] when that is not NULL,
+ * and cleared), else 0 / EHIP. */
 int lattice_batch_sync(lattice_batch_t* B, int32_t* member_flags);
 
 /* Last detailed error message of the batch handle, or "". */

@@ -6,7 +6,10 @@ tile (64, 128, 256: one lane per site), or split-column tiles (block 0:
 each column over several lanes, for classes whose members all have
 nv == cap), and resident workgroups per compute unit of the persistent
 launch (0 = one workgroup per tile) -- on the GPU with HIP events, on a
-sub-batch holding only that class's members, and keep the fastest.  Results are cached as JSON keyed by GPU architecture, class,
+sub-batch holding only that class's members, and keep the fastest.  Then,
+for batches that allow it, time the whole batch under the per-step
+schedule and under the resident one (a single launch per call with
+per-member step barriers) and keep the faster.  Results are cached as JSON keyed by GPU architecture, class,
 scheme and the class's size (log2 of its cell count), so later batches of
 similar shape reuse them without timing.
 """
@@ -139,6 +142,92 @@ def tune_batch(batch, flows, scheme: str = "koren", steps: int = 20,
         cache[key] = {"block": best[0], "grid_per_cu": best[1],
                       "ms_per_step": round(best[2], 5)}
         dirty = True
+    sched = tune_schedule(batch, flows, scheme, steps, graph_steps, cache,
+                          use_cache, log)
+    if sched is not None:
+        chosen["schedule"] = sched
+        dirty = dirty or sched[3]
     if dirty and use_cache:
         save_cache(cache, cache_path)
     return chosen
+
+
+RESIDENT_CAPS = (17, 33, 65, 129)
+# (workgroups per CU (0: as many as fit), items per work-counter fetch)
+RESIDENT_CANDIDATES = ((0, 4), (0, 8), (0, 16), (0, 32), (2, 16))
+# the schedules are compared over this many steps, the per-step one
+# replaying a graph of as many (as a long run does)
+SCHEDULE_STEPS = 50
+
+
+def tune_schedule(batch, flows, scheme, steps, graph_steps, cache, use_cache,
+                  log=None):
+    """With the per-class decompositions applied, time the whole batch
+    under the per-step schedule (graph replays) and the resident schedule
+    (each grid of RESIDENT_GRIDS) and keep the faster; only for batches
+    whose members all have nv in RESIDENT_CAPS (else None).  Returns
+    (mode name, grid_per_cu, ms_per_step, newly timed)."""
+    import numpy as np
+    import torch
+
+    from .lattice import PER_STEP, RESIDENT
+    if not all(m.nv in RESIDENT_CAPS for m in batch.members):
+        return None
+    key = (f"{_arch()}|schedule|{scheme}|n{len(batch.members)}|"
+           f"2^{int(round(math.log2(max(batch.total_cells, 1))))}")
+    if use_cache and key in cache:
+        c = cache[key]
+        if c["mode"] == "resident":
+            batch.schedule(RESIDENT, c["grid_per_cu"], c.get("chunk", 0))
+        else:
+            batch.schedule(PER_STEP)
+        return (c["mode"], c["grid_per_cu"], c.get("ms_per_step"), False)
+    rng = np.random.default_rng(0)
+    f = torch.from_numpy(batch.pack_state(
+        [rng.random((m.nv, m.nx)).astype(np.float32)
+         for m in batch.members])).cuda()
+    u = torch.from_numpy(batch.pack_flow(flows)).cuda()
+    n = min(SCHEDULE_STEPS,
+            min(max(1, (m.n_u_slices * m.u_hold) if m.u_hold else
+                    SCHEDULE_STEPS) for m in batch.members))
+    n = max(2, n - n % 2)
+    g = n
+
+    def timed():
+        batch.step(f, u, 2)  # warm-up (captures nothing: 2 eager steps)
+        batch.sync()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        batch.step(f, u, n, graph_steps=g)
+        e1.record()
+        torch.cuda.synchronize()
+        batch.sync()
+        return e0.elapsed_time(e1) / n
+
+    batch.schedule(PER_STEP)
+    best = ("per_step", g, timed())
+    if log:
+        log(f"autotune schedule: per step (graph of {g}): {best[2]:.4f} ms")
+    chunk = 0
+    for gpc, ck in RESIDENT_CANDIDATES:
+        try:
+            batch.schedule(RESIDENT, gpc, ck)
+        except Exception as e:  # noqa: BLE001 - a schedule that does not fit
+            if log:
+                log(f"autotune schedule: resident {gpc}/CU refused: {e}")
+            continue
+        ms = timed()
+        if log:
+            log(f"autotune schedule: resident, {gpc} workgroups per CU "
+                f"(0 = as many as fit), chunks of {ck}: {ms:.4f} ms")
+        if ms < best[2]:
+            best, chunk = ("resident", gpc, ms), ck
+    if best[0] == "resident":
+        batch.schedule(RESIDENT, best[1], chunk)
+    else:
+        batch.schedule(PER_STEP)
+    del f, u
+    cache[key] = {"mode": best[0], "grid_per_cu": best[1], "chunk": chunk,
+                  "ms_per_step": round(best[2], 5)}
+    return (best[0], best[1], best[2], True)

@@ -117,6 +117,226 @@ __global__ __launch_bounds__(parts_threads<NV>()) void k_batch1d_parts(
   }
 }
 
+// ---------------------------------------------------------------------
+// Resident multi-step form: one launch advances every member by all the
+// steps of a call.  The members are split among the XCDs (the chip's
+// accelerator dies, each with its own L2 cache shared by its compute
+// units); every tile of a member, at every step, is updated by a
+// workgroup of the member's XCD.  Each XCD has a work counter over its
+// (step, tile) items, numbered step-major with the tiles of one step
+// listed member by member; its workgroups take chunks of consecutive items
+// from it.  A member's tile of step t > 0 starts once the member's counter
+// of finished tiles shows all of its step t-1 tiles done: the pull
+// streaming of step t reads any of them, and they have finished reading the
+// buffer that step t writes.  Because producer and consumer share one L2,
+// a finished tile is published by waiting for the workgroup's stores to
+// reach the L2 before counting it (no L2 write-back, which publishing to
+// another XCD's L2 would need on every tile: measured 15x slower), and
+// consumed after invalidating the compute unit's L1.
+// Deadlock freedom: a workgroup publishes its finished items before it
+// ever waits, and only waits on items taken before its own, each held by a
+// running workgroup, so the earliest unfinished item never waits.  Every
+// class uses eight wavefronts per workgroup so that one kernel serves all
+// of them (split-column tiles of parts1d.h).
+template <int NV>
+struct ResidentShape;
+template <> struct ResidentShape<17> { static constexpr int P = 4; };
+template <> struct ResidentShape<33> { static constexpr int P = 4; };
+template <> struct ResidentShape<65> { static constexpr int P = 4; };
+template <> struct ResidentShape<129> { static constexpr int P = 8; };
+constexpr int kResW = 8;  // wavefronts per workgroup
+template <int NV>
+using ResTile = Parts1DTile<float, NV, ResidentShape<NV>::P, kResW>;
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int kResLds = cmax(cmax(ResTile<17>::SIZE, ResTile<33>::SIZE),
+                             cmax(ResTile<65>::SIZE, ResTile<129>::SIZE));
+
+// Tiles x0, x0 + G, ..., x0 + (n-1) G of member m at one step, software
+// pipelined: the loads of the next tile are in flight while the current
+// one is updated and stored (as in the per-step split-column kernel).
+// Every thread of the workgroup calls it; the tile LDS is free on return.
+template <int NV, bool KOREN>
+__device__ __forceinline__ void resident_run(float* tile,
+                                             const float* __restrict__ fin,
+                                             float* __restrict__ fout,
+                                             const float* __restrict__ u,
+                                             const BatchMember& m, int x0,
+                                             int n, int slice) {
+  constexpr int P = ResidentShape<NV>::P;
+  using PT = ResTile<NV>;
+  int jump = 0;  // (P s) mod nx, no division
+  for (int q = 0; q < P; ++q) {
+    jump += m.step_mod;
+    if (jump >= m.nx) jump -= m.nx;
+  }
+  const float* const src = fin + m.f_off;
+  float* const dst = fout + m.f_off;
+  const float* const us = u + m.u_off + (int64_t)slice * m.nx;
+  float r[PT::K];
+  PT::load(src, m.nx, x0, m.step_mod, m.init_off, jump, r);
+  for (int q = 0; q < n; ++q) {
+    const int xq = x0 + q * PT::G;
+    PT::put(tile, r);
+    // the flow value first: the memory counter is in order, and the
+    // collision must not wait for the next tile's loads
+    const float alpha = PT::alpha_at(us, m.nx, xq, m.alpha_scale);
+    __syncthreads();
+    // unconditional, so that the counter waits stay exact (past the last
+    // tile: idle loads of one element)
+    PT::load(src, m.nx, q + 1 < n ? xq + PT::G : xq, m.step_mod, m.init_off,
+             jump, r, q + 1 >= n);
+    PT::template collide<KOREN>(tile, alpha, m.nsub, m.beta, m.D);
+    __syncthreads();
+    PT::store(tile, dst, m.nx, xq);
+    __syncthreads();
+  }
+}
+
+template <bool KOREN>
+__device__ __forceinline__ void resident_dispatch(
+    float* tile, const float* __restrict__ fin, float* __restrict__ fout,
+    const float* __restrict__ u, const BatchMember& m, int x0, int n,
+    int slice) {
+  switch (m.nv) {
+    case 17: resident_run<17, KOREN>(tile, fin, fout, u, m, x0, n, slice); break;
+    case 33: resident_run<33, KOREN>(tile, fin, fout, u, m, x0, n, slice); break;
+    case 65: resident_run<65, KOREN>(tile, fin, fout, u, m, x0, n, slice); break;
+    default: resident_run<129, KOREN>(tile, fin, fout, u, m, x0, n, slice); break;
+  }
+}
+
+__device__ __forceinline__ int resident_g(int nv) {
+  switch (nv) {
+    case 17: return ResTile<17>::G;
+    case 33: return ResTile<33>::G;
+    case 65: return ResTile<65>::G;
+    default: return ResTile<129>::G;
+  }
+}
+
+// The XCD this workgroup runs on (hardware register XCC_ID, bits 0..3).
+__device__ __forceinline__ int xcc_id() {
+  return (int)__builtin_amdgcn_s_getreg(20 | (0 << 6) | (3 << 11)) & 15;
+}
+
+// This wavefront's stores have reached the L2 (vector memory counter at
+// zero; also a compiler barrier, so no store is scheduled after it).
+__device__ __forceinline__ void stores_in_l2() {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
+// Later loads of this wavefront see what other compute units of the XCD
+// wrote to the L2 before the counter it polled: the device-scope acquire
+// invalidates the compute unit's L1 (a workgroup-scope invalidate is a
+// no-op when a workgroup's wavefronts share one L1).
+__device__ __forceinline__ void drop_l1() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// b0 holds the state before local step 0; step t reads b0 (t even) or b1
+// and writes the other.  XCD x owns tiles[goff[x] .. goff[x+1]), one
+// step's items; its counter is sync[kResQStride x].  sync[kResAbort] is
+// the abort flag, sync[kResDone + m] member m's finished tiles; all zero at
+// launch.  A wait that polls more than wait_limit times (or any wait when
+// wait_limit < 0) raises the abort flag and ends the workgroup; the others
+// end at their next wait or when their queue runs out.
+template <bool KOREN>
+__global__ __launch_bounds__(64 * kResW) void k_batch_resident(
+    float* __restrict__ b0, float* __restrict__ b1,
+    const float* __restrict__ u, const BatchMember* __restrict__ mem,
+    const BatchTile* __restrict__ tiles, const int* __restrict__ goff,
+    int nxcd, const int* __restrict__ mtiles, const int* __restrict__ mflag,
+    int step0, int nsteps, int chunk, int* __restrict__ sync,
+    int wait_limit) {
+  __shared__ float tile[kResLds];
+  __shared__ int s_base[2];
+  __shared__ int s_go;
+  const int tid = (int)threadIdx.x;
+  const int x = xcc_id();
+  if (x >= nxcd) return;
+  const int g0 = goff[x], T = goff[x + 1] - g0;
+  if (T == 0) return;
+  const int total = T * nsteps;  // the host keeps it below 2^31 - grid chunk
+  int* const queue = sync + kResQStride * x;
+  int* const abort_flag = sync + kResAbort;
+  int* const done = sync + kResDone;
+  if (tid == 0)
+    s_base[0] = __hip_atomic_fetch_add(queue, chunk, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  int slot = 0;
+  int cur_m = -1, cur_t = -1, pend = 0;  // run of same member and step
+  bool stop = false;
+  // publish the finished tiles of the current run
+  auto flush = [&]() {
+    if (pend == 0) return;
+    stores_in_l2();
+    __syncthreads();
+    if (tid == 0)
+      __hip_atomic_fetch_add(&done[cur_m], pend, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    pend = 0;
+  };
+  while (!stop) {
+    const int base = s_base[slot];
+    if (base >= total) break;
+    // the next chunk's number travels while this one is worked on
+    if (tid == 0)
+      s_base[slot ^ 1] = __hip_atomic_fetch_add(queue, chunk,
+                                                __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+    const int end = base + chunk < total ? base + chunk : total;
+    // the chunk as runs of consecutive tiles of one member at one step
+    for (int i = base; i < end;) {
+      const int t = i / T;
+      const BatchTile tl = tiles[g0 + (i - t * T)];
+      const BatchMember m = mem[tl.member];
+      const int left = mtiles[tl.member] - tl.x0 / resident_g(m.nv);
+      const int n = end - i < left ? end - i : left;
+      i += n;
+      if (mflag[tl.member] != 0) continue;  // frozen members do nothing
+      if (tl.member != cur_m || t != cur_t) {
+        flush();
+        cur_m = tl.member;
+        cur_t = t;
+        if (t > 0) {
+          if (tid == 0) {
+            const int need = t * mtiles[tl.member];
+            int polls = 0, ok = 1;
+            while (__hip_atomic_load(&done[tl.member], __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT) < need) {
+              if (wait_limit < 0 || ++polls > wait_limit ||
+                  __hip_atomic_load(abort_flag, __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+              }
+              __builtin_amdgcn_s_sleep(2);
+            }
+            s_go = ok;
+          }
+          __syncthreads();
+          if (!s_go) {
+            stop = true;
+            break;
+          }
+          drop_l1();
+        }
+      }
+      float* const fin = (t & 1) ? b1 : b0;
+      float* const fout = (t & 1) ? b0 : b1;
+      const int sl = m.u_hold > 0 ? (step0 + t) / m.u_hold : 0;
+      resident_dispatch<KOREN>(tile, fin, fout, u, m, tl.x0, n, sl);
+      pend += n;
+    }
+    __syncthreads();  // s_base[slot ^ 1] is written
+    slot ^= 1;
+  }
+  if (!stop) flush();
+}
+
 // Per member: flag |= 1 if one of the slices the call uses has |u| past the
 // member's drift bound or non-finite.  Grid (chunks, members): the
 // workgroups of one member share its slices grid-stride.
@@ -184,6 +404,7 @@ __global__ void k_batch_moments_final(const double* __restrict__ ps,
 
 __global__ void k_set_int(int* p, int v) { *p = v; }
 __global__ void k_add_int(int* p, int v) { *p += v; }
+__global__ void k_or_int(const int* src, int* dst) { *dst |= *src; }
 __global__ void k_clear_ints(int* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
@@ -263,6 +484,67 @@ hipError_t launch_batch1d(const BatchLaunch& a, hipStream_t s) {
   }
 }
 
+int batch_resident_sites(int cap) {
+  switch (cap) {
+    case 17: return ResTile<17>::G;
+    case 33: return ResTile<33>::G;
+    case 65: return ResTile<65>::G;
+    case 129: return ResTile<129>::G;
+    default: return 0;
+  }
+}
+
+int batch_resident_threads() { return 64 * kResW; }
+
+hipError_t batch_resident_occupancy(int koren, int* blocks_per_cu) {
+  return koren ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                     blocks_per_cu, k_batch_resident<true>, 64 * kResW, 0)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                     blocks_per_cu, k_batch_resident<false>, 64 * kResW, 0);
+}
+
+hipError_t launch_batch_resident(const ResidentLaunch& a, hipStream_t s) {
+  auto go = [&](auto kernel) {
+    hipLaunchKernelGGL(kernel, dim3(a.grid), dim3(64 * kResW), 0, s, a.b0,
+                       a.b1, a.u, a.mem, a.tiles, a.goff, a.nxcd, a.mtiles,
+                       a.mflag, a.step0, a.nsteps, a.chunk, a.sync,
+                       a.wait_limit);
+  };
+  if (a.koren)
+    go(k_batch_resident<true>);
+  else
+    go(k_batch_resident<false>);
+  return hipGetLastError();
+}
+
+// After a resident launch: every XCD with items must have handed all of
+// them out (a workgroup ran there); otherwise the launch did not complete
+// and the abort flag is raised.
+__global__ void k_resident_check(int* sync, const int* goff, int nxcd,
+                                 int nsteps) {
+  for (int x = 0; x < nxcd; ++x) {
+    const int64_t need = (int64_t)(goff[x + 1] - goff[x]) * nsteps;
+    if (need > 0 && (int64_t)sync[kResQStride * x] < need)
+      sync[kResAbort] = 1;
+  }
+}
+
+hipError_t launch_resident_check(int* sync, const int* goff, int nxcd,
+                                 int nsteps, hipStream_t s) {
+  hipLaunchKernelGGL(k_resident_check, dim3(1), dim3(1), 0, s, sync, goff,
+                     nxcd, nsteps);
+  return hipGetLastError();
+}
+
+__global__ void k_xcc_probe(int* out) {
+  if (threadIdx.x == 0) out[blockIdx.x] = xcc_id();
+}
+
+hipError_t launch_xcc_probe(int* out, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_xcc_probe, dim3(nblocks), dim3(64), 0, s, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_batch_cfl(const float* u, const BatchMember* mem, int count,
                             int64_t nsteps, int64_t max_values, int strict,
                             int* mflag, hipStream_t s) {
@@ -294,6 +576,11 @@ hipError_t launch_set_int(int* p, int v, hipStream_t s) {
 
 hipError_t launch_add_int(int* p, int v, hipStream_t s) {
   hipLaunchKernelGGL(k_add_int, dim3(1), dim3(1), 0, s, p, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_or_int(const int* src, int* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_or_int, dim3(1), dim3(1), 0, s, src, dst);
   return hipGetLastError();
 }
 

@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -55,6 +56,18 @@ struct lattice_batch {
   hipGraphExec_t gexec = nullptr;
   const void *g_a = nullptr, *g_b = nullptr, *g_u = nullptr;
   int g_steps = 0;
+  // resident multi-step schedule
+  int mode = LATTICE_BATCH_PER_STEP;
+  int r_grid = 0;
+  int wait_limit = 1 << 22;
+  lat::BatchTile* d_rtiles = nullptr;  // one step's items, XCD by XCD
+  int r_span = 0;            // most items of one XCD per step
+  int r_nxcd = 0;
+  int r_chunk = 4;
+  int* d_goff = nullptr;     // XCD x owns d_rtiles[goff[x] .. goff[x+1])
+  int* d_rmtiles = nullptr;  // tiles per member
+  int* d_sync = nullptr;     // work counters, abort flag, done per member
+  int* d_aborted = nullptr;  // some chunk gave up since the last sync
   char msg[512];
 };
 
@@ -362,6 +375,123 @@ int lattice_batch_tune(lattice_batch_t* B, int32_t cap, int32_t block,
   return LATTICE_OK;
 }
 
+int lattice_batch_schedule(lattice_batch_t* B, int32_t mode,
+                           int32_t grid_per_cu, int32_t chunk,
+                           int64_t wait_limit) {
+  if (!B) return LATTICE_EINVAL;
+  B->msg[0] = 0;
+  if (mode != LATTICE_BATCH_PER_STEP && mode != LATTICE_BATCH_RESIDENT)
+    return berr(B, LATTICE_EINVAL, "unknown schedule %d", mode);
+  if (grid_per_cu < 0 || grid_per_cu > 16)
+    return berr(B, LATTICE_EINVAL, "grid_per_cu must be 0..16");
+  if (chunk < 0 || chunk > 64)
+    return berr(B, LATTICE_EINVAL, "chunk must be 0..64");
+  if (wait_limit >= (1LL << 31))
+    return berr(B, LATTICE_EINVAL, "wait_limit must be below 2^31");
+  if (mode == LATTICE_BATCH_PER_STEP) {
+    B->mode = mode;
+    return LATTICE_OK;
+  }
+  for (int r = 0; r < B->count; ++r) {
+    const int nv = B->desc[r].nv;
+    if (lat::batch_resident_sites(nv) == 0)
+      return berr(B, LATTICE_ENOTSUP,
+                  "resident schedule: member %d has nv %d (needs 17, 33, 65 "
+                  "or 129)", r, nv);
+  }
+  BCHK(B, hipStreamSynchronize(B->stream));
+  int occ = 0;
+  BCHK(B, lat::batch_resident_occupancy(B->scheme == LATTICE_KOREN, &occ));
+  if (occ < 1)
+    return berr(B, LATTICE_ENOTSUP, "resident kernel does not fit a CU");
+  const int gpc = grid_per_cu == 0 ? occ : grid_per_cu;
+  // which XCDs the workgroups of a launch land on: every id below the
+  // count must appear (a probe of many workgroups)
+  int nxcd = 0;
+  {
+    const int nb = 8 * B->ncu;
+    int* d_ids = nullptr;
+    BCHK(B, hipMalloc(&d_ids, sizeof(int) * nb));
+    std::vector<int> ids(nb);
+    hipError_t e = lat::launch_xcc_probe(d_ids, nb, B->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(B->stream);
+    if (e == hipSuccess)
+      e = hipMemcpy(ids.data(), d_ids, sizeof(int) * nb,
+                    hipMemcpyDeviceToHost);
+    (void)hipFree(d_ids);
+    BCHK(B, e);
+    bool seen[lat::kResMaxXcd] = {};
+    for (int v : ids) {
+      if (v < 0 || v >= lat::kResMaxXcd)
+        return berr(B, LATTICE_ENOTSUP, "unexpected XCD id %d", v);
+      seen[v] = true;
+      if (v + 1 > nxcd) nxcd = v + 1;
+    }
+    for (int v = 0; v < nxcd; ++v)
+      if (!seen[v])
+        return berr(B, LATTICE_ENOTSUP, "no workgroup landed on XCD %d", v);
+  }
+  // members to XCDs: largest first, each to the least loaded XCD (cells)
+  std::vector<int> order(B->count), owner(B->count);
+  for (int r = 0; r < B->count; ++r) order[r] = r;
+  auto cells = [&](int r) { return B->desc[r].nx * (int64_t)B->desc[r].nv; };
+  std::sort(order.begin(), order.end(), [&](int a, int b) {
+    return cells(a) != cells(b) ? cells(a) > cells(b) : a < b;
+  });
+  std::vector<int64_t> load(nxcd, 0);
+  for (int r : order) {
+    int best = 0;
+    for (int x = 1; x < nxcd; ++x)
+      if (load[x] < load[best]) best = x;
+    owner[r] = best;
+    load[best] += cells(r);
+  }
+  std::vector<lat::BatchTile> t;
+  std::vector<int> goff(nxcd + 1, 0), per(B->count);
+  int span = 1;
+  for (int x = 0; x < nxcd; ++x) {
+    goff[x] = (int)t.size();
+    for (int r = 0; r < B->count; ++r) {
+      if (owner[r] != x) continue;
+      const int g = lat::batch_resident_sites(B->desc[r].nv);
+      for (int64_t x0 = 0; x0 < B->desc[r].nx; x0 += g)
+        t.push_back({r, (int32_t)x0});
+      per[r] = (int)((B->desc[r].nx + g - 1) / g);
+    }
+    if ((int)t.size() - goff[x] > span) span = (int)t.size() - goff[x];
+  }
+  goff[nxcd] = (int)t.size();
+  if ((int64_t)t.size() > (1 << 24))
+    return berr(B, LATTICE_ENOTSUP, "resident schedule: too many tiles");
+  if (B->d_rtiles) (void)hipFree(B->d_rtiles);
+  B->d_rtiles = nullptr;
+  BCHK(B, hipMalloc(&B->d_rtiles, sizeof(lat::BatchTile) * t.size()));
+  BCHK(B, hipMemcpy(B->d_rtiles, t.data(), sizeof(lat::BatchTile) * t.size(),
+                    hipMemcpyHostToDevice));
+  if (!B->d_goff)
+    BCHK(B, hipMalloc(&B->d_goff, sizeof(int) * (lat::kResMaxXcd + 1)));
+  BCHK(B, hipMemcpy(B->d_goff, goff.data(), sizeof(int) * (nxcd + 1),
+                    hipMemcpyHostToDevice));
+  if (!B->d_rmtiles) BCHK(B, hipMalloc(&B->d_rmtiles, sizeof(int) * B->count));
+  BCHK(B, hipMemcpy(B->d_rmtiles, per.data(), sizeof(int) * B->count,
+                    hipMemcpyHostToDevice));
+  if (!B->d_sync)
+    BCHK(B, hipMalloc(&B->d_sync, sizeof(int) * (lat::kResDone + B->count)));
+  if (!B->d_aborted) {
+    BCHK(B, hipMalloc(&B->d_aborted, sizeof(int)));
+    BCHK(B, lat::launch_clear_ints(B->d_aborted, 1, B->stream));
+    BCHK(B, hipStreamSynchronize(B->stream));
+  }
+  B->r_span = span;
+  B->r_nxcd = nxcd;
+  B->r_chunk = chunk == 0 ? 4 : chunk;
+  B->r_grid = gpc * B->ncu;
+  B->wait_limit = wait_limit < 0 ? -1
+                  : wait_limit == 0 ? (1 << 22) : (int)wait_limit;
+  B->mode = mode;
+  return LATTICE_OK;
+}
+
 int lattice_batch_step(lattice_batch_t* B, float* f, const float* u,
                        int64_t nsteps, int32_t use_graph,
                        int32_t graph_steps) {
@@ -400,6 +530,42 @@ int lattice_batch_step(lattice_batch_t* B, float* f, const float* u,
   } else {
     bufs[0] = f;
     bufs[1] = B->scratch;
+  }
+  if (B->mode == LATTICE_BATCH_RESIDENT) {
+    // chunks of steps whose items stay countable in 32 bits
+    const int64_t per =
+        ((int64_t)0x7fffffff - 2 * (int64_t)B->r_grid * B->r_chunk) /
+        B->r_span;
+    for (int64_t s0 = 0; s0 < nsteps;) {
+      const int64_t n = nsteps - s0 < per ? nsteps - s0 : per;
+      BCHK(B, lat::launch_clear_ints(B->d_sync, lat::kResDone + B->count,
+                                     B->stream));
+      lat::ResidentLaunch a;
+      a.koren = B->scheme == LATTICE_KOREN;
+      a.grid = B->r_grid;
+      a.b0 = bufs[s0 & 1];
+      a.b1 = bufs[(s0 & 1) ^ 1];
+      a.u = u;
+      a.mem = B->d_mem;
+      a.tiles = B->d_rtiles;
+      a.goff = B->d_goff;
+      a.nxcd = B->r_nxcd;
+      a.mtiles = B->d_rmtiles;
+      a.mflag = B->d_flag;
+      a.step0 = (int)s0;
+      a.nsteps = (int)n;
+      a.chunk = B->r_chunk;
+      a.sync = B->d_sync;
+      a.wait_limit = B->wait_limit;
+      BCHK(B, lat::launch_batch_resident(a, B->stream));
+      BCHK(B, lat::launch_resident_check(B->d_sync, B->d_goff, B->r_nxcd,
+                                         (int)n, B->stream));
+      // the abort flag of this launch is kept for lattice_batch_sync
+      BCHK(B, lat::launch_or_int(B->d_sync + lat::kResAbort, B->d_aborted,
+                                 B->stream));
+      s0 += n;
+    }
+    return LATTICE_OK;
   }
   int64_t done = 0;
   if (use_graph && nsteps >= graph_steps) {
@@ -462,6 +628,18 @@ int lattice_batch_moments(lattice_batch_t* B, const float* f, double* out) {
 int lattice_batch_sync(lattice_batch_t* B, int32_t* member_flags) {
   if (!B) return LATTICE_EINVAL;
   BCHK(B, hipStreamSynchronize(B->stream));
+  if (B->d_aborted) {
+    int ab = 0;
+    BCHK(B, hipMemcpy(&ab, B->d_aborted, sizeof(int), hipMemcpyDeviceToHost));
+    if (ab) {
+      BCHK(B, lat::launch_clear_ints(B->d_aborted, 1, B->stream));
+      BCHK(B, hipStreamSynchronize(B->stream));
+      return berr(B, LATTICE_ETIMEOUT,
+                  "resident schedule: a workgroup waited past the wait "
+                  "limit for a member's previous step; the state is "
+                  "undefined");
+    }
+  }
   std::vector<int> fl(B->count);
   BCHK(B, hipMemcpy(fl.data(), B->d_flag, sizeof(int) * B->count,
                     hipMemcpyDeviceToHost));
@@ -494,6 +672,11 @@ int lattice_batch_destroy(lattice_batch_t* B) {
     if (B->ev_join[i]) (void)hipEventDestroy(B->ev_join[i]);
   }
   if (B->ev_fork) (void)hipEventDestroy(B->ev_fork);
+  if (B->d_rtiles) (void)hipFree(B->d_rtiles);
+  if (B->d_goff) (void)hipFree(B->d_goff);
+  if (B->d_rmtiles) (void)hipFree(B->d_rmtiles);
+  if (B->d_sync) (void)hipFree(B->d_sync);
+  if (B->d_aborted) (void)hipFree(B->d_aborted);
   if (B->d_mem) (void)hipFree(B->d_mem);
   if (B->d_flag) (void)hipFree(B->d_flag);
   if (B->d_base) (void)hipFree(B->d_base);

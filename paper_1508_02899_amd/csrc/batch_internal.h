@@ -53,6 +53,43 @@ struct BatchLaunch {
 };
 
 hipError_t launch_batch1d(const BatchLaunch& a, hipStream_t s);
+
+// The resident multi-step kernel (all classes, split-column tiles).
+// Layout of its synchronisation words (ints, zero at launch): the work
+// counter of XCD x at kResQStride x (x < kResMaxXcd, one 128-byte line
+// each), the abort flag at kResAbort, member m's finished tiles at
+// kResDone + m.
+constexpr int kResQStride = 32, kResMaxXcd = 16;
+constexpr int kResAbort = kResQStride * kResMaxXcd;
+constexpr int kResDone = kResAbort + kResQStride;
+struct ResidentLaunch {
+  int koren;
+  int grid;
+  float* b0;  // state before local step 0
+  float* b1;
+  const float* u;
+  const BatchMember* mem;
+  const BatchTile* tiles;  // one step's items, XCD by XCD, member by member
+  const int* goff;         // XCD x owns tiles[goff[x] .. goff[x+1])
+  int nxcd;
+  const int* mtiles;  // tiles per member
+  const int* mflag;
+  int step0;   // step index of local step 0 within the call (flow slices)
+  int nsteps;  // (largest goff span) * nsteps + grid * chunk < 2^31
+  int chunk;   // items per work-counter fetch
+  int* sync;
+  int wait_limit;
+};
+hipError_t launch_batch_resident(const ResidentLaunch& a, hipStream_t s);
+// Sites per tile of a capacity class in the resident kernel (0: none).
+int batch_resident_sites(int cap);
+int batch_resident_threads();
+hipError_t batch_resident_occupancy(int koren, int* blocks_per_cu);
+// Raise the abort flag if some XCD did not hand out all of its items.
+hipError_t launch_resident_check(int* sync, const int* goff, int nxcd,
+                                 int nsteps, hipStream_t s);
+// out[b] = XCD of workgroup b, for nblocks workgroups.
+hipError_t launch_xcc_probe(int* out, int nblocks, hipStream_t s);
 // Sites per split-column tile of a capacity class (0: no split-column
 // kernel for it).
 int batch_parts_sites(int cap);
@@ -68,5 +105,6 @@ hipError_t launch_batch_moments(const float* f, const BatchPlane* planes,
 hipError_t launch_set_int(int* p, int v, hipStream_t s);
 hipError_t launch_add_int(int* p, int v, hipStream_t s);
 hipError_t launch_clear_ints(int* p, int n, hipStream_t s);
+hipError_t launch_or_int(const int* src, int* dst, hipStream_t s);
 
 }  // namespace lat

@@ -645,6 +645,8 @@ const char* lattice_strerror(int code) {
     case LATTICE_ENOTSUP: return "no kernel compiled for this lattice";
     case LATTICE_ETOOBIG:
       return "state larger than the static scratch of lattice_step_noalloc";
+    case LATTICE_ETIMEOUT:
+      return "resident batched launch gave up waiting for a member's step";
     default: return "unknown error";
   }
 }

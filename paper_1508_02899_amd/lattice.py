@@ -21,6 +21,8 @@ SCHEMES = {"upwind": UPWIND, "koren": KOREN}
 
 OK, EINVAL, ECFL, EDIFF, EHIP, ENOMEM, ENONFINITE, ENOTSUP, ETOOBIG = (
     0, -1, -2, -3, -4, -5, -6, -7, -8)
+ETIMEOUT = -9
+PER_STEP, RESIDENT = 0, 1  # lattice_batch_schedule modes
 NOALLOC_MAX_BYTES = 64 << 20  # LATTICE_NOALLOC_MAX_BYTES
 
 # every symbol declared in include/lattice.h
@@ -34,7 +36,8 @@ EXPORTS = (
     "lattice_flow1d_modes", "lattice_flow2d_modes", "lattice_s1",
     "lattice_profile_read", "lattice_destroy", "lattice_strerror",
     "lattice_last_error", "lattice_batch_init", "lattice_batch_layout",
-    "lattice_batch_tune", "lattice_batch_step", "lattice_batch_moments",
+    "lattice_batch_tune", "lattice_batch_schedule", "lattice_batch_step",
+    "lattice_batch_moments",
     "lattice_batch_sync", "lattice_batch_destroy", "lattice_batch_last_error",
     "lattice_restrict",
     "lattice_mlp_create", "lattice_mlp_set_params", "lattice_mlp_get_params",
@@ -150,6 +153,8 @@ def load_library(path: str = LIB_PATH):
     L.lattice_batch_layout.argtypes = [vp, pi64, pi64, pi64, pi64]
     L.lattice_batch_tune.argtypes = [vp, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.c_int32]
+    L.lattice_batch_schedule.argtypes = [vp, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_int32, i64]
     L.lattice_batch_step.argtypes = [vp, vp, vp, i64, ctypes.c_int32,
                                      ctypes.c_int32]
     L.lattice_batch_moments.argtypes = [vp, vp, ctypes.POINTER(dbl)]
@@ -619,9 +624,19 @@ class Batch:
         self._check(self.lib.lattice_batch_tune(self._B, cap, block,
                                                 grid_per_cu))
 
+    def schedule(self, mode: int, grid_per_cu: int = 0, chunk: int = 0,
+                 wait_limit: int = 0):
+        """PER_STEP (launches per step and class) or RESIDENT (one launch
+        per call, per-member step barriers on device counters, members
+        split among the XCDs)."""
+        self._check(self.lib.lattice_batch_schedule(
+            self._B, int(mode), int(grid_per_cu), int(chunk),
+            int(wait_limit)))
+
     def step(self, f, u, nsteps: int, graph_steps: int = 0):
         """Advance every member by nsteps (asynchronous); graph_steps > 0
-        replays a captured HIP graph of that many (even) steps.  f: packed
+        replays a captured HIP graph of that many (even) steps (per-step
+        schedule only).  f: packed
         FP32 state of total_cells elements; u: packed FP32 flows of at
         least total_u elements."""
         torch = _torch()

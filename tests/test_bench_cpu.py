@@ -51,6 +51,14 @@ def test_recorded_counters_match_the_kernel_sources():
         with open(os.path.join(d, f)) as fh:
             t = json.load(fh)
         w = bench.WORKLOADS[t["workload"]]
-        assert t["kernel_hash"] == bench.kernel_hash(w["dim"]), f
-        assert bench.load_traffic(t["workload"]) == t["bytes_per_launch"]
-        assert 0.99 < t["traffic_over_algorithmic"] < 1.05, f
+        if w.get("batch"):
+            assert t["kernel_hash"] == bench.kernel_hash("batch"), f
+            assert (bench.load_traffic(t["workload"], "batch") ==
+                    t["bytes_per_step"])
+        else:
+            assert t["kernel_hash"] == bench.kernel_hash(w["dim"]), f
+            assert bench.load_traffic(t["workload"]) == t["bytes_per_launch"]
+        # the batched kernel writes 1.15x its state (reads 1.05x): the
+        # members' packed planes put tile rows at arbitrary alignments
+        bound = 1.15 if w.get("batch") else 1.05
+        assert 0.99 < t["traffic_over_algorithmic"] < bound, f

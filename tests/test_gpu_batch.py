@@ -246,10 +246,23 @@ def test_batch_256_members_full_size_sampled():
     say(f"  batch of 256: {b.total_cells} cells")
     fp = b.pack_state(states)
     f = torch.from_numpy(fp.copy()).cuda()
-    b.step(f, torch.from_numpy(b.pack_flow(flows)).cuda(), nsteps,
-           graph_steps=2)
+    u = torch.from_numpy(b.pack_flow(flows)).cuda()
+    b.step(f, u, nsteps, graph_steps=2)
     b.sync()
     out = b.unpack_state(f.cpu().numpy())
+    # the resident schedule on the same batch: the same bits
+    from paper_1508_02899_amd.lattice import RESIDENT
+    for cap in (33, 65, 129):
+        b.tune(cap, 0, 0)
+    f.copy_(torch.from_numpy(fp))
+    b.step(f, u, nsteps)
+    b.sync()
+    split = f.cpu().numpy()
+    b.schedule(RESIDENT)
+    f.copy_(torch.from_numpy(fp))
+    b.step(f, u, nsteps)
+    b.sync()
+    assert np.array_equal(f.cpu().numpy(), split)
     sizes = [m.nx * m.nv for m in mems]
     pick = {int(np.argmax(sizes)), int(np.argmin(sizes))}
     pick |= set(int(i) for i in rng.choice(256, 3, replace=False))
@@ -258,4 +271,92 @@ def test_batch_256_members_full_size_sampled():
         err = rel_l2(out[k], want)
         say(f"  member {k} nx={mems[k].nx} nv={mems[k].nv}: {err:.2e}")
         assert err <= FP32_REL_L2
+    b.close()
+
+
+def _split_batch(scheme, nsteps, seed):
+    from paper_1508_02899_amd import Batch
+    rng = np.random.default_rng(seed)
+    mems, states, flows = _members(rng, SPLIT_SPECS, nsteps)
+    b = Batch(mems, scheme=scheme)
+    for cap in (17, 33, 65, 129):
+        b.tune(cap, 0, 0)
+    return b, mems, states, flows
+
+
+@pytest.mark.parametrize("scheme", ["koren", "upwind"])
+@pytest.mark.parametrize("nsteps", [7, 12])
+def test_batch_resident_schedule_matches_per_step_and_oracle(scheme, nsteps):
+    """The resident schedule (one launch per call, per-member step barriers
+    on device counters, members split among the XCDs) gives exactly the
+    per-step result, for odd and even step counts, several grid sizes and
+    work chunks, and every member matches the oracle."""
+    from paper_1508_02899_amd.lattice import PER_STEP, RESIDENT
+    b, mems, states, flows = _split_batch(scheme, nsteps, 31)
+    fp, up = b.pack_state(states), b.pack_flow(flows)
+    ref = _run(b, fp, up, nsteps)
+    for gpc, chunk in ((0, 0), (1, 1), (3, 8), (0, 64)):
+        b.schedule(RESIDENT, grid_per_cu=gpc, chunk=chunk)
+        got = _run(b, fp, up, nsteps)
+        assert np.array_equal(got, ref), f"grid per CU {gpc}, chunk {chunk}"
+    for m, f0, u, g in zip(mems, states, flows, b.unpack_state(got)):
+        err = rel_l2(g, _oracle_member(m, f0, u, nsteps, scheme))
+        say(f"  member nx={m.nx} nv={m.nv}: rel L2 {err:.2e}")
+        assert err <= FP32_REL_L2
+    b.schedule(PER_STEP)
+    assert np.array_equal(_run(b, fp, up, nsteps), ref)
+    b.close()
+
+
+def test_batch_resident_freezes_only_the_violating_member():
+    import torch
+    from paper_1508_02899_amd.lattice import ECFL, RESIDENT
+    b, mems, states, flows = _split_batch("koren", 6, 32)
+    flows[3] = flows[3] * 1000.0
+    b.schedule(RESIDENT)
+    f = torch.from_numpy(b.pack_state(states)).cuda()
+    b.step(f, torch.from_numpy(b.pack_flow(flows)).cuda(), 6)
+    rc, flags = b.sync(check=False)
+    assert rc == ECFL
+    assert list(flags) == [0, 0, 0, 1, 0, 0]
+    out = b.unpack_state(f.cpu().numpy())
+    assert np.array_equal(out[3], states[3])
+    for k in (0, 2, 5):
+        assert rel_l2(out[k], _oracle_member(mems[k], states[k], flows[k],
+                                             6)) <= FP32_REL_L2
+    b.close()
+
+
+def test_batch_resident_wait_limit_reports_a_timeout():
+    """Forced from the host: with a negative wait limit every wait gives up
+    at once, the launch ends early and sync reports ETIMEOUT (once); the
+    next calls with the normal limit are exact again."""
+    import torch
+    from paper_1508_02899_amd.lattice import ETIMEOUT, RESIDENT
+    b, mems, states, flows = _split_batch("koren", 6, 33)
+    fp, up = b.pack_state(states), b.pack_flow(flows)
+    ref = _run(b, fp, up, 6)
+    b.schedule(RESIDENT, wait_limit=-1)
+    f = torch.from_numpy(fp.copy()).cuda()
+    b.step(f, torch.from_numpy(up).cuda(), 6)
+    rc, _ = b.sync(check=False)
+    assert rc == ETIMEOUT
+    assert b.sync(check=False)[0] == 0
+    b.schedule(RESIDENT)
+    assert np.array_equal(_run(b, fp, up, 6), ref)
+    b.close()
+
+
+def test_batch_resident_needs_split_column_velocity_counts():
+    from paper_1508_02899_amd import Batch, LatticeError
+    from paper_1508_02899_amd.lattice import RESIDENT
+    rng = np.random.default_rng(34)
+    mems, states, flows = _members(rng, [(200, 31, 1.0, 0.2, 0, 0.4),
+                                         (100, 33, 1.0, 0.2, 0, 0.4)], 4)
+    b = Batch(mems)
+    with pytest.raises(LatticeError):
+        b.schedule(RESIDENT)
+    out = b.unpack_state(_run(b, b.pack_state(states), b.pack_flow(flows), 4))
+    for m, f0, u, got in zip(mems, states, flows, out):
+        assert rel_l2(got, _oracle_member(m, f0, u, 4)) <= FP32_REL_L2
     b.close()
