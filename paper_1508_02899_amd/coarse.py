@@ -307,51 +307,57 @@ def rollout_loss(track: Track, ref: Track, dx: float, from_step: int):
 
 
 # packed parameter layout: W1[8][64], b1[64], W2[64][64], b2[64], w3[64], b3
+_OFF_B1, _OFF_W2 = 512, 576
 _OFF_B2, _OFF_W3, _OFF_B3, _NPARAMS = 4672, 4736, 4800, 4801
 
 
 def train_a_posteriori(mlp: Mlp, coarse_spec: LatticeSpec, St: float,
                        line_eps: float, runs, *, dt: float, tau_p: float,
                        kappa: float, levels: int, from_step: int,
-                       iters: int = 40, pairs: int = 8, sigma: float = 0.05,
-                       lr: float = 0.04, patience: int = 8, seed: int = 0,
+                       iters: int = 80, pairs: int = 8, sigma: float = 0.05,
+                       lr: float = 0.04, patience: int = 12, seed: int = 0,
                        log=None):
-    """A-posteriori (unrolled) training of the network's last layers (b2,
-    w3, b3) on whole coarse runs: ``runs`` lists (ref, g0, flow) triples,
-    and the loss is the mean over them of rollout_loss of the coarse
-    lattice with the network attached, run from g0 under flow against the
-    restricted fine run ref (see fine_reference), so the network is judged
-    on the states its own corrections produce, over every step of each
-    run.  The run has no adjoint here, so the gradient is estimated by
-    evolution strategies: ``pairs`` antithetic Gaussian perturbations of
-    relative size sigma per iteration (each a complete set of runs),
-    centred-rank fitness shaping and an Adam step whose size falls from lr
-    to lr/10 along a half cosine, all in units of each parameter group's
-    RMS.  The search stops early once ``patience`` iterations in a row
-    have not lowered the lowest loss seen; those parameters are written
-    into mlp.  Host arithmetic touches only these 129 numbers.  Returns
-    (loss before, loss after, per-iteration losses)."""
+    """A-posteriori (unrolled) training of the network's hidden biases and
+    output layer (b1, b2, w3, b3: 193 numbers) on whole coarse runs:
+    ``runs`` lists (ref, g0, flow) triples, and the loss is the mean over
+    them of rollout_loss of the coarse lattice with the network attached,
+    run from g0 under flow against the restricted fine run ref (see
+    fine_reference), so the network is judged on the states its own
+    corrections produce, over every step of each run.  The run has no
+    adjoint here, so the gradient is estimated by evolution strategies:
+    ``pairs`` antithetic Gaussian perturbations of relative size sigma per
+    iteration (each a complete set of runs), centred-rank fitness shaping
+    and an Adam step, all in units of each parameter group's RMS.  The step
+    size starts at lr; a step that raises the loss above the lowest seen
+    is taken back and the step size halved (down to lr/64), a step that
+    lowers it lets the step size grow by a quarter (up to lr).  The search
+    stops once ``patience`` iterations in a row have not lowered the lowest
+    loss; those parameters are written into mlp.  Host arithmetic touches
+    only these 193 numbers.  Returns (loss before, loss after,
+    per-iteration losses)."""
     import numpy as np
     torch = _torch()
     rng = np.random.default_rng(seed)
     P0 = np.asarray(mlp.get_params(), dtype=np.float64)
-    tail = slice(_OFF_B2, _NPARAMS)
-    th0 = P0[tail].copy()
+    idx = np.concatenate([np.arange(_OFF_B1, _OFF_W2),
+                          np.arange(_OFF_B2, _NPARAMS)])
+    th0 = P0[idx].copy()
 
     def rms(v):
         return float(np.sqrt(np.mean(v * v)))
 
-    w3s = max(rms(P0[_OFF_W3:_OFF_B3]), 1e-4)
+    nb1, nb2 = _OFF_W2 - _OFF_B1, _OFF_W3 - _OFF_B2
     S = np.empty_like(th0)
-    S[:_OFF_W3 - _OFF_B2] = max(rms(P0[_OFF_B2:_OFF_W3]), 1e-2)
-    S[_OFF_W3 - _OFF_B2:] = w3s
+    S[:nb1] = max(rms(P0[_OFF_B1:_OFF_W2]), 1e-2)
+    S[nb1:nb1 + nb2] = max(rms(P0[_OFF_B2:_OFF_W3]), 1e-2)
+    S[nb1 + nb2:] = max(rms(P0[_OFF_W3:_OFF_B3]), 1e-4)
     lat = Lattice(replace(coarse_spec, u_hold=1))
     mlp.attach(lat, St, line_eps)
     work = torch.empty_like(runs[0][1])
 
     def loss_at(z):
         P = P0.copy()
-        P[tail] = th0 + S * z
+        P[idx] = th0 + S * z
         mlp.set_params(P.astype(np.float32))
         total = 0.0
         for ref, g0, flow in runs:
@@ -364,7 +370,7 @@ def train_a_posteriori(mlp: Mlp, coarse_spec: LatticeSpec, St: float,
     m = np.zeros_like(z)
     v = np.zeros_like(z)
     first = best = loss_at(z)
-    zbest, since = z.copy(), 0
+    zbest, since, step = z.copy(), 0, lr
     hist = [first]
     for it in range(1, iters + 1):
         eps = rng.standard_normal((pairs, z.size))
@@ -377,22 +383,25 @@ def train_a_posteriori(mlp: Mlp, coarse_spec: LatticeSpec, St: float,
             pairs * sigma)
         m = 0.9 * m + 0.1 * g
         v = 0.999 * v + 0.001 * g * g
-        step = lr * (0.1 + 0.45 * (1 + math.cos(math.pi * (it - 1) / iters)))
-        z = z - step * (m / (1 - 0.9 ** it)) / (
+        z_try = z - step * (m / (1 - 0.9 ** it)) / (
             np.sqrt(v / (1 - 0.999 ** it)) + 1e-8)
-        cur = loss_at(z)
+        cur = loss_at(z_try)
         hist.append(cur)
         if cur < best:
-            best, zbest, since = cur, z.copy(), 0
+            best, zbest, since = cur, z_try.copy(), 0
+            z = z_try
+            step = min(lr, 1.25 * step)
         else:
             since += 1
+            z = zbest.copy()
+            step = max(lr / 64, 0.5 * step)
         if log is not None:
             log(f"a-posteriori iteration {it}: loss {cur:.4e} (best "
-                f"{best:.4e}, start {first:.4e})")
+                f"{best:.4e}, start {first:.4e}, step {step:.3g})")
         if since >= patience:
             break
     P = P0.copy()
-    P[tail] = th0 + S * zbest
+    P[idx] = th0 + S * zbest
     mlp.set_params(P.astype(np.float32))
     mlp.attach(lat, St, line_eps)
     lat.sync()
@@ -500,7 +509,7 @@ def build_and_evaluate(n: int, nv_fine: int, St: float, kappa: float,
                        lrs=(3e-3, 1e-3, 3e-4), adam_steps: int = 27000,
                        train_eps: float = 8e-3, es_eps: float = 1.8e-2,
                        es_steps: int = 200, es_every: int = 25,
-                       es_offsets=(0, 200), es_iters: int = 40,
+                       es_offsets=(0, 200), es_iters: int = 80,
                        es_pairs: int = 8,
                        thresholds=(8e-3, 1.2e-2, 1.8e-2, 2.4e-2, 3.2e-2,
                                    4.8e-2, 6.4e-2),
@@ -518,7 +527,8 @@ def build_and_evaluate(n: int, nv_fine: int, St: float, kappa: float,
 
     1. a-priori training on least-norm targets from a fine run under the
        training flow (faces below train_eps of the site mass dropped);
-    2. a-posteriori training of the last layers on whole coarse runs
+    2. a-posteriori training of the hidden biases and the output layer on
+       whole coarse runs
        against the restricted fine runs, from the initial state under the
        training flow from each of its slices es_offsets
        (train_a_posteriori, face threshold es_eps);
