@@ -12,6 +12,9 @@ def pytest_configure(config):
     config.addinivalue_line(
         "markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: longer CPU test")
+    config.addinivalue_line(
+        "markers", "gpu_long: GPU test of several minutes, run by naming the "
+        "marker (-m gpu_long -s); not part of -m gpu")
 
 
 def pytest_collection_modifyitems(config, items):
@@ -26,5 +29,5 @@ def pytest_collection_modifyitems(config, items):
         return
     skip = pytest.mark.skip(reason="no GPU visible")
     for item in items:
-        if "gpu" in item.keywords:
+        if "gpu" in item.keywords or "gpu_long" in item.keywords:
             item.add_marker(skip)

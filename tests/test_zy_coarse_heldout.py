@@ -1,32 +1,35 @@
 """The coarse-model workflow judged under a flow it never saw, at the size
 the coarse workload runs: 2D 256^2 sites, fine 65^2 velocities against the
-stride-4 coarse 17^2 lattice with the learned face-flux correction, St = 5,
-Koren.  The network is trained a priori on fine-run targets and a
-posteriori on whole coarse runs under one flow (the a-posteriori stage
-shortened here to one run and 10 iterations, to keep the test short); the
-face threshold and output scale are chosen under a second flow; the
-evaluation runs the fine, plain coarse and corrected coarse lattices side by
-side under a third.  Target: at least 4x the fine lattice's throughput with
-the velocity-variance and distance-averaged <rho_r^2> errors (Sec. 4.2.1)
-within 2 % of the restricted fine state.  St = 0.5 and 2 do not meet it
-(their variance errors stay at a few per cent) and are not asserted."""
+stride-4 coarse 17^2 lattice with the learned face-flux correction, Koren.
+The network is trained a priori on fine-run targets and a posteriori on
+whole coarse runs under one flow (the a-posteriori stage shortened here to
+one run and fewer iterations, to keep the test short); the face threshold
+and output scale are chosen under a second flow; the evaluation runs the
+fine, plain coarse and corrected coarse lattices side by side under a
+third.  Target: at least 4x the fine lattice's throughput with the
+velocity-variance and distance-averaged <rho_r^2> errors (Sec. 4.2.1)
+within 2 % of the restricted fine state, asserted for the Stokes numbers
+that meet it (0.5 and 5); St = 2 does not (its variance error stays near
+3.5 %) and is not asserted.  St = 5 meets it with a short a-posteriori
+stage (one run, 10 iterations: 20 s); St = 0.5 only with the full one
+(two runs, up to 80 iterations: about four minutes, over the time a GPU
+test may run without output), so that case carries the gpu_long marker
+and runs when named: pytest -m gpu_long -s."""
 import pytest
 
 from helpers import say
 
-pytestmark = pytest.mark.gpu
 
-
-def test_held_out_flow_meets_the_target_at_st5():
+def _held_out(St, es_offsets, es_iters):
     import torch
     from paper_1508_02899_amd import coarse as CC
     torch.cuda.set_device(0)
-    n, nvf, vmax, St, kappa = 256, 65, 3.0, 5.0, 1e-4
+    n, nvf, vmax, kappa = 256, 65, 3.0, 1e-4
     flows = CC.workload_flows(n, nvf, vmax,
-                              {"train": 260, "valid": 225, "eval": 225})
+                              {"train": 400, "valid": 225, "eval": 225})
     say(f"  coarse workflow, {n}^2 sites, St {St}")
     r = CC.build_and_evaluate(n, nvf, St, kappa, vmax, flows,
-                              es_offsets=(0,), es_iters=10,
+                              es_offsets=es_offsets, es_iters=es_iters,
                               time_warmup=5, time_n=20,
                               log=lambda m: say("  " + m))
     e = r["errors_vs_restricted_fine"]
@@ -45,3 +48,13 @@ def test_held_out_flow_meets_the_target_at_st5():
     assert e["mlp"]["variance"] <= 0.02
     assert e["mlp"]["rho_r2"] <= 0.02
     assert r["meets_target"]
+
+
+@pytest.mark.gpu
+def test_held_out_flow_meets_the_target_at_st5():
+    _held_out(5.0, (0,), 10)
+
+
+@pytest.mark.gpu_long
+def test_held_out_flow_meets_the_target_at_st05():
+    _held_out(0.5, (0, 200), 80)
