@@ -497,16 +497,26 @@ def _trace_table(trace, workload, cmd):
 
 # dominant kernel family of the workloads whose summaries hold only the
 # kernel-time table
-TRACE_ONLY_KERNELS = {"batch-256x1d": "k_batch1d",
-                      "coarse-mlp-256x256": "k_mlp_correct17"}
+TRACE_ONLY_KERNELS = {"coarse-mlp-256x256": "k_mlp_correct17"}
 
 
 def summarize_trace(args):
     """Write the kernel-time summary of one workload under profiles/ from a
-    rocprofv3 --kernel-trace --stats output folder."""
+    rocprofv3 --kernel-trace --stats output folder.  For the coarse
+    workload also the average of the correction kernel's --steps longest
+    dispatches: the timed launches with every face corrected, which the
+    bench's roofline line describes."""
     kern = TRACE_ONLY_KERNELS[args.workload]
     cmd = args.command or "(command not recorded)"
-    _, lines = _trace_table(_rocpd(args.summarize_trace), args.workload, cmd)
+    db = _rocpd(args.summarize_trace)
+    _, lines = _trace_table(db, args.workload, cmd)
+    durs = sorted((r[0] for r in db.execute(
+        "select end - start from kernels where name like ?",
+        (f"%{kern}%",))), reverse=True)[:args.steps]
+    if durs:
+        lines += ["", f"`{kern}`, the {len(durs)} longest dispatches (the "
+                  "timed launches with every face corrected): average "
+                  f"{sum(durs) / len(durs) / 1e3:.1f} us."]
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     path = os.path.join(ROOT, "profiles",
                         f"{kern}_{args.workload}_kernel_stats.md")
