@@ -850,9 +850,20 @@ __global__ __launch_bounds__(64 * kRedWaves) void k_grad_reduce(
   const int q = (int)threadIdx.x >> 6, j = (int)threadIdx.x & 63;
   const int p = (int)blockIdx.x * 64 + j;
   float s = 0.f;
-  if (p <= kNParams)
-    for (int r = q; r < nrows; r += kRedWaves)
-      s += partial[(size_t)r * (kNParams + 1) + p];
+  if (p <= kNParams) {
+    // the loads of eight rows in flight together, added in row order
+    const float* col = partial + p;
+    const size_t rs = (size_t)kRedWaves * (kNParams + 1);
+    int r = q;
+    for (; r + 7 * kRedWaves < nrows; r += 8 * kRedWaves) {
+      float v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v[k] = col[(size_t)r * (kNParams + 1) + k * rs];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) s += v[k];
+    }
+    for (; r < nrows; r += kRedWaves) s += col[(size_t)r * (kNParams + 1)];
+  }
   sh[q][j] = s;
   __syncthreads();
   if (q != 0 || p > kNParams) return;
