@@ -341,10 +341,14 @@ const char* lattice_last_error(const lattice_t* L);
  * update of lattice_step (Sec. 2, Eqs. 3-5), FP32 state.
  *
  * Packed layouts (device, FP32): member m's state occupies
- * f[f_off[m] .. f_off[m] + nv_m*nx_m) in the layout [nv_m][nx_m]; its flow
- * occupies u[u_off[m] .. u_off[m] + n_u_slices_m*nx_m) as [slices][nx_m].
- * Offsets are assigned by lattice_batch_init in member order (query them
- * with lattice_batch_layout).
+ * f[f_off[m] .. f_off[m] + nv_m*pitch_m) in the layout [nv_m][pitch_m],
+ * of which elements 0 .. nx_m-1 of each velocity plane are the lattice's
+ * cells and the rest padding that no kernel reads or writes; pitch_m is
+ * nx_m rounded up to a multiple of 64, so that every plane starts on a
+ * 256-byte boundary.  Its flow occupies u[u_off[m] .. u_off[m] +
+ * n_u_slices_m*nx_m) as [slices][nx_m].  Offsets and pitches are assigned
+ * by lattice_batch_init in member order (lattice_batch_layout,
+ * lattice_batch_plane_pitch).
  *
  * Two schedules (lattice_batch_schedule).  Per step (the default): one
  * lattice_batch_step call queues, per time step, one persistent kernel per
@@ -378,10 +382,18 @@ int lattice_batch_init(const lattice_member_desc* members, int32_t count,
                        int32_t scheme, int32_t vstride, void* stream,
                        lattice_batch_t** out);
 
-/* Packed offsets (host arrays of count elements, may be NULL) and totals. */
+/* Packed offsets (host arrays of count elements, may be NULL) and the
+ * element counts of the packed state (padding included) and flow
+ * buffers. */
 int lattice_batch_layout(const lattice_batch_t* B, int64_t* f_off,
                          int64_t* u_off, int64_t* total_cells,
                          int64_t* total_u);
+
+/* Plane pitch of every member (host array of count elements, may be NULL)
+ * and the number of lattice cells of the batch (sum of nv_m nx_m; may be
+ * NULL).  EINVAL. */
+int lattice_batch_plane_pitch(const lattice_batch_t* B, int64_t* pitch,
+                              int64_t* cells);
 
 /* Work decomposition of one capacity class (cap = 9, 17, 33, 65 or 129):
  * block = lanes (= sites) per tile (64, 128 or 256), one lane per site with

@@ -30,7 +30,8 @@ __global__ __launch_bounds__(256) void k_batch1d(
     if (x >= m.nx) continue;
     const int sl = m.u_hold > 0 ? step / m.u_hold : 0;
     const float ux = u[m.u_off + (int64_t)sl * m.nx + x];
-    column1d<float, CAP, KOREN>(fin + m.f_off, fout + m.f_off, x, m.nx, m.nv,
+    column1d<float, CAP, KOREN>(fin + m.f_off, fout + m.f_off, x, m.nx,
+                                m.pitch, m.nv,
                                 m.h, m.step_mod, m.init_off, m.nsub,
                                 ux * m.alpha_scale, m.beta, m.D);
   }
@@ -88,8 +89,8 @@ __global__ __launch_bounds__(parts_threads<NV>()) void k_batch1d_parts(
       jump += m.step_mod;
       if (jump >= m.nx) jump -= m.nx;
     }
-    PT::load(fin + m.f_off, m.nx, tl.x0, m.step_mod, m.init_off, jump, r,
-             idle);
+    PT::load(fin + m.f_off, m.nx, m.pitch, tl.x0, m.step_mod, m.init_off,
+             jump, r, idle);
   };
   float r[PT::K];
   int w = next((int)blockIdx.x);
@@ -111,7 +112,7 @@ __global__ __launch_bounds__(parts_threads<NV>()) void k_batch1d_parts(
     issue(wn < ntiles ? wn : w, r, wn >= ntiles);
     PT::template collide<KOREN>(tile, alpha, m.nsub, m.beta, m.D);
     __syncthreads();
-    PT::template store<NT>(tile, fout + m.f_off, m.nx, tl.x0);
+    PT::template store<NT>(tile, fout + m.f_off, m.nx, m.pitch, tl.x0);
     __syncthreads();  // the tile is refilled for the next work item
     w = wn;
   }
@@ -173,7 +174,7 @@ __device__ __forceinline__ void resident_run(float* tile,
   float* const dst = fout + m.f_off;
   const float* const us = u + m.u_off + (int64_t)slice * m.nx;
   float r[PT::K];
-  PT::load(src, m.nx, x0, m.step_mod, m.init_off, jump, r);
+  PT::load(src, m.nx, m.pitch, x0, m.step_mod, m.init_off, jump, r);
   for (int q = 0; q < n; ++q) {
     const int xq = x0 + q * PT::G;
     PT::put(tile, r);
@@ -183,11 +184,11 @@ __device__ __forceinline__ void resident_run(float* tile,
     __syncthreads();
     // unconditional, so that the counter waits stay exact (past the last
     // tile: idle loads of one element)
-    PT::load(src, m.nx, q + 1 < n ? xq + PT::G : xq, m.step_mod, m.init_off,
-             jump, r, q + 1 >= n);
+    PT::load(src, m.nx, m.pitch, q + 1 < n ? xq + PT::G : xq, m.step_mod,
+             m.init_off, jump, r, q + 1 >= n);
     PT::template collide<KOREN>(tile, alpha, m.nsub, m.beta, m.D);
     __syncthreads();
-    PT::store(tile, dst, m.nx, xq);
+    PT::store(tile, dst, m.nx, m.pitch, xq);
     __syncthreads();
   }
 }

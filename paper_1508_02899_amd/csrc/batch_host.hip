@@ -19,6 +19,7 @@ namespace {
 constexpr int kNumCls = 5;
 constexpr int kCaps[kNumCls] = {9, 17, 33, 65, 129};
 constexpr int kSide = 3;  // parallel streams for the classes beyond the first
+constexpr int64_t kPlaneAlign = 64;  // elements: planes on 256-byte boundaries
 
 struct Cls {
   int cap = 0;
@@ -37,7 +38,8 @@ struct lattice_batch {
   int count = 0, scheme = 0, vstride = 1;
   std::vector<lattice_member_desc> desc;
   std::vector<lat::BatchMember> mem;
-  int64_t total_cells = 0, total_u = 0;
+  int64_t total_cells = 0, total_u = 0;  // packed elements (padding included)
+  int64_t cells = 0;                      // lattice cells
   hipStream_t stream = nullptr;
   hipStream_t cap = nullptr;  // private stream the HIP graph is captured on
   hipStream_t side[kSide] = {};
@@ -234,6 +236,11 @@ int lattice_batch_init(const lattice_member_desc* members, int32_t count,
     m.nsub = 1;
     m.u_hold = (int32_t)d.u_hold;
     m.plane0 = (int32_t)planes.size();
+    // planes start on 256-byte boundaries: a tile's rows then never share
+    // a cache line with another tile's (measured: without, the kernels
+    // write 1.16x the state, the partial lines written back twice)
+    const int64_t pitch = (d.nx + kPlaneAlign - 1) / kPlaneAlign * kPlaneAlign;
+    m.pitch = (int32_t)pitch;
     const bool drag = isfinite(d.tau_p);
     m.alpha_scale = drag ? (float)(d.dt / (dv * d.tau_p)) : 0.f;
     m.beta = drag ? (float)(d.dt / d.tau_p) : 0.f;
@@ -252,8 +259,9 @@ int lattice_batch_init(const lattice_member_desc* members, int32_t count,
     m.dx = d.dx;
     m.dv = dv;
     for (int j = 0; j < d.nv; ++j)
-      planes.push_back({foff + (int64_t)j * d.nx, (int32_t)d.nx, 0});
-    foff += (int64_t)d.nv * d.nx;
+      planes.push_back({foff + (int64_t)j * pitch, (int32_t)d.nx, 0});
+    foff += (int64_t)d.nv * pitch;
+    B->cells += (int64_t)d.nv * d.nx;
     uoff += d.n_u_slices * d.nx;
     B->cls[cap_class(d.nv)].members.push_back(r);
     B->cls[cap_class(d.nv)].bytes += d.nx * d.nv * (int64_t)sizeof(float);
@@ -340,6 +348,15 @@ int lattice_batch_layout(const lattice_batch_t* B, int64_t* f_off,
   }
   if (total_cells) *total_cells = B->total_cells;
   if (total_u) *total_u = B->total_u;
+  return LATTICE_OK;
+}
+
+int lattice_batch_plane_pitch(const lattice_batch_t* B, int64_t* pitch,
+                              int64_t* cells) {
+  if (!B) return LATTICE_EINVAL;
+  for (int r = 0; r < B->count; ++r)
+    if (pitch) pitch[r] = B->mem[r].pitch;
+  if (cells) *cells = B->cells;
   return LATTICE_OK;
 }
 

@@ -9,7 +9,7 @@ namespace lat {
 
 // One realization, as the kernels see it.
 struct BatchMember {
-  int64_t f_off;      // element offset of its state [nv][nx]
+  int64_t f_off;      // element offset of its state [nv][pitch]
   int64_t u_off;      // element offset of its flow slices [slices][nx]
   int32_t nx, nv, h;
   int32_t step_mod;   // vstride mod nx
@@ -17,6 +17,7 @@ struct BatchMember {
   int32_t nsub;       // collision sub-steps per step
   int32_t u_hold;     // steps per flow slice (0 = one slice)
   int32_t plane0;     // index of its first velocity plane in plane tables
+  int32_t pitch;      // elements from one velocity plane to the next
   float alpha_scale;  // dt_s / (dv tau_p)
   float beta;         // dt_s / tau_p
   float D;            // kappa dt_s / dv^2

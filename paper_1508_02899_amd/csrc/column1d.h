@@ -8,11 +8,13 @@ namespace lat {
 
 // The whole 1D update of one site x (one lane): pull the velocity column,
 // nsub x [drift, diffusion] in registers, store.  alpha = dt_s u(x) /
-// (dv tau_p) is the drift of the zero-velocity cell in cell widths.
+// (dv tau_p) is the drift of the zero-velocity cell in cell widths.  Plane
+// j starts pitch elements after plane j-1 (pitch >= nx).
 template <typename T, int CAP, bool KOREN>
 __device__ __forceinline__ void column1d(const T* __restrict__ fin,
                                          T* __restrict__ fout, int x, int nx,
-                                         int nv, int h, int step_mod,
+                                         int pitch, int nv, int h,
+                                         int step_mod,
                                          int init_off, int nsub, T alpha,
                                          T beta, T D) {
   // ---- 1. pull streaming: source site of cell j is (x - shift*(j-h)) mod nx
@@ -22,7 +24,7 @@ __device__ __forceinline__ void column1d(const T* __restrict__ fin,
 #pragma unroll
   for (int j = 0; j < CAP; ++j) {
     if (j < nv) {
-      c[j] = fin[(size_t)j * nx + xs];
+      c[j] = fin[(size_t)j * pitch + xs];
       xs -= step_mod;
       if (xs < 0) xs += nx;
     } else {
@@ -82,7 +84,7 @@ __device__ __forceinline__ void column1d(const T* __restrict__ fin,
   // ---- 3. store
 #pragma unroll
   for (int j = 0; j < CAP; ++j)
-    if (j < nv) fout[(size_t)j * nx + x] = c[j];
+    if (j < nv) fout[(size_t)j * pitch + x] = c[j];
 }
 
 

@@ -101,13 +101,15 @@ struct Parts1DTile {
   static constexpr int STRIDE = C::STRIDE, SKEW = C::SKEW, SIZE = C::SIZE;
 
   // 1a. pull streaming: plane j of site x comes from (x - s(j-h)) mod nx;
-  // jump = (P s) mod nx, step_mod = s mod nx, init_off = (s h) mod nx.
+  // jump = (P s) mod nx, step_mod = s mod nx, init_off = (s h) mod nx;
+  // plane j starts pitch elements after plane j-1 (pitch >= nx).
   // idle: the same loads (so that the memory-counter waits after them stay
   // exact) all from the first element of fin; r is not used then.
   __device__ __forceinline__ static void load(const T* __restrict__ fin,
-                                              int nx, int x0, int step_mod,
-                                              int init_off, int jump,
-                                              T (&r)[K], bool idle = false) {
+                                              int nx, int pitch, int x0,
+                                              int step_mod, int init_off,
+                                              int jump, T (&r)[K],
+                                              bool idle = false) {
     const int tid = (int)threadIdx.x;
     const int fj0 = tid / G;
     const int fs = tid - fj0 * G;
@@ -123,7 +125,7 @@ struct Parts1DTile {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int j = fj0 + P * k;
-      const size_t e = idle ? 0 : (size_t)j * nx + xs;
+      const size_t e = idle ? 0 : (size_t)j * pitch + xs;
       r[k] = (k < K - 1 || j < NV) ? fin[e] : T(0);
       xs -= jump;
       if (xs < 0) xs += nx;
@@ -256,7 +258,7 @@ struct Parts1DTile {
   template <bool NT = false>
   __device__ __forceinline__ static void store(const T* __restrict__ tile,
                                                T* __restrict__ fout, int nx,
-                                               int x0) {
+                                               int pitch, int x0) {
     const int tid = (int)threadIdx.x;
     const int fj0 = tid / G;
     const int fs = tid - fj0 * G;
@@ -266,7 +268,7 @@ struct Parts1DTile {
       for (int k = 0; k < K; ++k) {
         const int j = fj0 + P * k;
         if (k < K - 1 || j < NV) {
-          T* const q = &fout[(size_t)j * nx + ox];
+          T* const q = &fout[(size_t)j * pitch + ox];
           if constexpr (NT)
             __builtin_nontemporal_store(tile[C::row(j) + fs], q);
           else
@@ -283,17 +285,17 @@ struct Parts1DTile {
 template <typename T, int NV, int P, int WGW, bool KOREN>
 __device__ __forceinline__ void parts1d_tile(
     const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict__ u,
-    T* __restrict__ tile, int nx, int x0, int step_mod, int init_off,
-    int jump, int nsub, T alpha_scale, T beta, T D) {
+    T* __restrict__ tile, int nx, int pitch, int x0, int step_mod,
+    int init_off, int jump, int nsub, T alpha_scale, T beta, T D) {
   using PT = Parts1DTile<T, NV, P, WGW>;
   T r[PT::K];
-  PT::load(fin, nx, x0, step_mod, init_off, jump, r);
+  PT::load(fin, nx, pitch, x0, step_mod, init_off, jump, r);
   PT::put(tile, r);
   __syncthreads();
   const T alpha = PT::alpha_at(u, nx, x0, alpha_scale);
   PT::template collide<KOREN>(tile, alpha, nsub, beta, D);
   __syncthreads();
-  PT::store(tile, fout, nx, x0);
+  PT::store(tile, fout, nx, pitch, x0);
 }
 
 }  // namespace lat

@@ -25,7 +25,7 @@ __global__ __launch_bounds__(256) void k_step1d(
   const int b = xcd_remap(blockIdx.x, nblocks);
   const int x = b * 256 + (int)threadIdx.x;
   if (x >= nx) return;
-  column1d<T, CAP, KOREN>(fin, fout, x, nx, nv, h, step_mod, init_off, nsub,
+  column1d<T, CAP, KOREN>(fin, fout, x, nx, nx, nv, h, step_mod, init_off, nsub,
                           u[x] * alpha_scale, beta, D);
 }
 

@@ -20,7 +20,7 @@ __global__ __launch_bounds__(64 * WGW) void k_step1d_parts(
   __shared__ T tile[C::SIZE];
   if (*flag != 0) return;  // uniform over the grid
   const int xg = xcd_remap(blockIdx.x, nblocks);
-  parts1d_tile<T, NV, P, WGW, KOREN>(fin, fout, u, tile, nx, xg * C::G,
+  parts1d_tile<T, NV, P, WGW, KOREN>(fin, fout, u, tile, nx, nx, xg * C::G,
                                      step_mod, init_off, jump, nsub,
                                      alpha_scale, beta, D);
 }

@@ -36,7 +36,8 @@ EXPORTS = (
     "lattice_flow1d_modes", "lattice_flow2d_modes", "lattice_s1",
     "lattice_profile_read", "lattice_destroy", "lattice_strerror",
     "lattice_last_error", "lattice_batch_init", "lattice_batch_layout",
-    "lattice_batch_tune", "lattice_batch_schedule", "lattice_batch_step",
+    "lattice_batch_plane_pitch", "lattice_batch_tune",
+    "lattice_batch_schedule", "lattice_batch_step",
     "lattice_batch_moments",
     "lattice_batch_sync", "lattice_batch_destroy", "lattice_batch_last_error",
     "lattice_restrict",
@@ -151,6 +152,7 @@ def load_library(path: str = LIB_PATH):
     L.lattice_batch_init.argtypes = [pmem, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.c_int32, vp, ctypes.POINTER(vp)]
     L.lattice_batch_layout.argtypes = [vp, pi64, pi64, pi64, pi64]
+    L.lattice_batch_plane_pitch.argtypes = [vp, pi64, pi64]
     L.lattice_batch_tune.argtypes = [vp, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.c_int32]
     L.lattice_batch_schedule.argtypes = [vp, ctypes.c_int32, ctypes.c_int32,
@@ -586,9 +588,15 @@ class Batch:
         tc, tu = ctypes.c_int64(), ctypes.c_int64()
         self._check(self.lib.lattice_batch_layout(h, fo, uo, ctypes.byref(tc),
                                                   ctypes.byref(tu)))
+        pt = (ctypes.c_int64 * n)()
+        cells = ctypes.c_int64()
+        self._check(self.lib.lattice_batch_plane_pitch(h, pt,
+                                                       ctypes.byref(cells)))
         self.f_off = list(fo)
         self.u_off = list(uo)
-        self.total_cells = tc.value
+        self.pitch = list(pt)
+        self.total_elems = tc.value  # packed state elements (padding too)
+        self.total_cells = cells.value  # lattice cells
         self.total_u = tu.value
 
     def _check(self, rc):
@@ -602,16 +610,19 @@ class Batch:
         return rc
 
     def pack_state(self, states):
-        """Concatenate per-member [nv, nx] arrays into one packed vector."""
+        """Place per-member [nv, nx] arrays into one packed vector (each
+        velocity plane at its member's pitch; padding zero)."""
         import numpy as np
-        out = np.empty(self.total_cells, dtype=np.float32)
-        for m, o, a in zip(self.members, self.f_off, states):
-            out[o:o + m.nv * m.nx] = np.asarray(a, np.float32).ravel()
+        out = np.zeros(self.total_elems, dtype=np.float32)
+        for m, o, p, a in zip(self.members, self.f_off, self.pitch, states):
+            out[o:o + m.nv * p].reshape(m.nv, p)[:, :m.nx] = \
+                np.asarray(a, np.float32).reshape(m.nv, m.nx)
         return out
 
     def unpack_state(self, flat):
-        return [flat[o:o + m.nv * m.nx].reshape(m.nv, m.nx)
-                for m, o in zip(self.members, self.f_off)]
+        """Per-member [nv, nx] views of a packed state."""
+        return [flat[o:o + m.nv * p].reshape(m.nv, p)[:, :m.nx]
+                for m, o, p in zip(self.members, self.f_off, self.pitch)]
 
     def pack_flow(self, flows):
         import numpy as np
@@ -637,10 +648,10 @@ class Batch:
         """Advance every member by nsteps (asynchronous); graph_steps > 0
         replays a captured HIP graph of that many (even) steps (per-step
         schedule only).  f: packed
-        FP32 state of total_cells elements; u: packed FP32 flows of at
+        FP32 state of total_elems elements; u: packed FP32 flows of at
         least total_u elements."""
         torch = _torch()
-        fp = require_tensor(f, "f", torch.float32, numel=self.total_cells,
+        fp = require_tensor(f, "f", torch.float32, numel=self.total_elems,
                             cuda=False)
         up = require_tensor(u, "u", torch.float32, min_numel=self.total_u,
                             cuda=False)
@@ -651,7 +662,7 @@ class Batch:
 
     def moments(self, f):
         import numpy as np
-        fp = require_tensor(f, "f", _torch().float32, numel=self.total_cells)
+        fp = require_tensor(f, "f", _torch().float32, numel=self.total_elems)
         out = (ctypes.c_double * (6 * len(self.members)))()
         self._check(self.lib.lattice_batch_moments(self._B, fp, out))
         return np.array(out).reshape(len(self.members), 6)

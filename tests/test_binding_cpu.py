@@ -48,13 +48,15 @@ def test_require_tensor_checks_each_property():
     (torch.zeros(100), torch.zeros(40), TypeError),              # on the CPU
 ])
 def test_batch_step_refuses_bad_buffers(f, u, err):
-    b = _fake(B.Batch, total_cells=100, total_u=40, _B=None, members=[])
+    b = _fake(B.Batch, total_elems=100, total_cells=90, total_u=40, _B=None,
+              members=[])
     with pytest.raises(err):
         b.step(f, u, 1)
 
 
 def test_batch_moments_refuses_bad_state():
-    b = _fake(B.Batch, total_cells=100, total_u=40, _B=None, members=[])
+    b = _fake(B.Batch, total_elems=100, total_cells=90, total_u=40, _B=None,
+              members=[])
     with pytest.raises(ValueError):
         b.moments(torch.zeros(101))
     with pytest.raises(TypeError):
