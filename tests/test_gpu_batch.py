@@ -360,3 +360,31 @@ def test_batch_resident_needs_split_column_velocity_counts():
     for m, f0, u, got in zip(mems, states, flows, out):
         assert rel_l2(got, _oracle_member(m, f0, u, 4)) <= FP32_REL_L2
     b.close()
+
+
+def test_batch_velocity_stride_two_both_schedules():
+    """Velocity stride 2 (each velocity index shifts 2(j-h) cells): the
+    per-step and the resident schedules give the same bits, and every
+    member matches the oracle run with the same stride."""
+    import oracle
+    from paper_1508_02899_amd import Batch
+    from paper_1508_02899_amd.lattice import RESIDENT
+    nsteps = 5
+    rng = np.random.default_rng(35)
+    mems, states, flows = _members(rng, SPLIT_SPECS, nsteps)
+    b = Batch(mems, vstride=2)
+    for cap in (17, 33, 65, 129):
+        b.tune(cap, 0, 0)
+    fp, up = b.pack_state(states), b.pack_flow(flows)
+    ref = _run(b, fp, up, nsteps)
+    b.schedule(RESIDENT)
+    assert np.array_equal(_run(b, fp, up, nsteps), ref)
+    for m, f0, u, got in zip(mems, states, flows, b.unpack_state(ref)):
+        want = oracle.step(f0.astype(np.float64),
+                           u.astype(np.float64)[:, None, :], dim=1, dx=m.dx,
+                           tau_p=m.tau_p, kappa=m.kappa, dt=m.dt,
+                           nsteps=nsteps, u_hold=m.u_hold, s=2)
+        err = rel_l2(got, want)
+        say(f"  member nx={m.nx} nv={m.nv}, stride 2: rel L2 {err:.2e}")
+        assert err <= FP32_REL_L2
+    b.close()
