@@ -409,6 +409,20 @@ def train_a_posteriori(mlp: Mlp, coarse_spec: LatticeSpec, St: float,
     return first, best, hist
 
 
+def choose_setting(table: dict, speed: dict, min_speedup: float):
+    """The (threshold, scale) pair of ``table`` ({(threshold, scale):
+    (variance error, <rho_r^2> error)}) with the smallest larger error
+    among those whose threshold reaches min_speedup in ``speed``
+    ({threshold: speed-up}); if none does, the best pair of the fastest
+    threshold.  Ties go to the pair listed first."""
+    ok = [k for k in table if speed[k[0]] >= min_speedup]
+    if ok:
+        return min(ok, key=lambda k: max(table[k]))
+    fast = max(speed, key=lambda e: speed[e])
+    return min([k for k in table if k[0] == fast],
+               key=lambda k: max(table[k]))
+
+
 def select_on_validation(fine_spec: LatticeSpec, coarse_spec: LatticeSpec,
                          mlp: Mlp, St: float, f0_fine, flow, *, steps: int,
                          dt: float, tau_p: float, kappa: float, thresholds,
@@ -465,13 +479,7 @@ def select_on_validation(fine_spec: LatticeSpec, coarse_spec: LatticeSpec,
                         kappa=kappa, warmup=time_warmup, steps=time_steps_n,
                         mlp=mlp, St=St, line_eps=eps)
         speed[eps] = ms_fine / ms
-    ok = [k for k in table if speed[k[0]] >= min_speedup]
-    if ok:
-        best = min(ok, key=lambda k: max(table[k]))
-    else:
-        fast = max(thresholds, key=lambda e: speed[e])
-        best = min([k for k in table if k[0] == fast],
-                   key=lambda k: max(table[k]))
+    best = choose_setting(table, speed, min_speedup)
     P = P0.copy()
     P[_OFF_W3:] *= best[1]
     mlp.set_params(P)
