@@ -71,12 +71,14 @@ struct Step2D {
   // One row t: c holds row t after streaming (when t < NV).  Reads state
   // `in`, writes state `out`; stores the finished row t-3 when t >= 3.
   // STEADY: 3 <= t < NV, where every row-range condition below holds, so
-  // the steady loop carries no selects for them.
+  // the steady loop carries no selects for them.  MODE (steady rows only):
+  // which split half of the vy drift to skip, see A_y below (0: none, 1: g-,
+  // 2: g+, 3: decided on this row).
   // emit(i, v) receives cell i of the finished row t-3.
-  template <bool STEADY, typename Emit>
+  template <bool STEADY, int MODE, typename Emit>
   __device__ __forceinline__ static void row(
-      const int t, const T (&c)[W], const YState<T, W>& in,
-      YState<T, W>& out, const T (&nxp)[W + 2], const T (&nxm)[W + 2],
+      const int t, const T (&c)[W], YState<T, W>& st,
+      const T (&nxp)[W + 2], const T (&nxm)[W + 2],
       const T ay, const T beta, const T D, const bool first, const bool last,
       const int lane_l, const int lane_r, Emit&& emit) {
     T q[W];  // row t after A_x (zero past the last row)
@@ -133,26 +135,64 @@ struct Step2D {
     const bool fpv = STEADY || (t >= 1 && t <= NV - 1);
     const bool fmv = STEADY || (t >= 2 && t <= NV);
     T a[W];
+    // The streamed state is updated in place (each cell's old values are
+    // read before they are replaced).  With beta >= 0 the vy drift falls
+    // along the rows, so a split half that is zero on every lane of the
+    // wavefront stays zero: once nu(t) >= 0 everywhere, g- of rows t-2..t is
+    // zero and so is its flux through face t-1, and its state (gm1, em1)
+    // already holds zeros; once nu(t-1) <= 0 everywhere, the g+ flux of
+    // face t is zero, gp1 already holds zero, and dpp1 is not read again
+    // (later rows skip g+ as well; the rows past the last plane force that
+    // flux to zero).  Steady rows may skip such a half: M = 1 skips g-,
+    // M = 2 skips g+, M = 0 computes both.  The caller guarantees the
+    // condition of a skip it asks for (MODE 1 or 2) or leaves it to this row
+    // (MODE 3).  The results differ from the full computation at most in the
+    // sign of a zero.
+    auto ay_cells = [&](auto mode) {
+      constexpr int M = decltype(mode)::value;
 #pragma unroll
-    for (int i = 0; i < W; ++i) {
-      const T gpv = nyp * q[i], gmv = nym * q[i];
-      const T dpp = gpv - in.gp1[i];
-      T Fp = in.gp1[i];
-      if (KOREN) Fp += koren(dpp, in.dpp1[i]);
-      if (!STEADY) Fp = fpv ? Fp : T(0);
-      const T em = in.gm1[i] - gmv;
-      T Fm = in.gm1[i];
-      if (KOREN) Fm += koren(in.em1[i], em);
-      if (!STEADY) Fm = fmv ? Fm : T(0);
-      const T Fface = in.Fp1[i] + Fm;  // total flux through face t-1
-      a[i] = in.acc2[i] - Fface;       // A_y output of row t-2
-      out.acc2[i] = in.c1[i] + Fface;
-      out.c1[i] = q[i];
-      out.Fp1[i] = Fp;
-      out.gp1[i] = gpv;
-      out.dpp1[i] = dpp;
-      out.gm1[i] = gmv;
-      out.em1[i] = em;
+      for (int i = 0; i < W; ++i) {
+        T Fface = st.Fp1[i];  // g+ flux of face t-1 (previous row)
+        if (M != 2) {
+          const T gpv = nyp * q[i];
+          const T dpp = gpv - st.gp1[i];
+          T Fp = st.gp1[i];
+          if (KOREN) Fp += koren(dpp, st.dpp1[i]);
+          if (!STEADY) Fp = fpv ? Fp : T(0);
+          st.Fp1[i] = Fp;
+          st.gp1[i] = gpv;
+          st.dpp1[i] = dpp;
+        } else {
+          st.Fp1[i] = T(0);
+        }
+        if (M != 1) {
+          const T gmv = nym * q[i];
+          const T em = st.gm1[i] - gmv;
+          T Fm = st.gm1[i];
+          if (KOREN) Fm += koren(st.em1[i], em);
+          if (!STEADY) Fm = fmv ? Fm : T(0);
+          Fface = Fface + Fm;  // total flux through face t-1
+          st.gm1[i] = gmv;
+          st.em1[i] = em;
+        }
+        a[i] = st.acc2[i] - Fface;  // A_y output of row t-2
+        st.acc2[i] = st.c1[i] + Fface;
+        st.c1[i] = q[i];
+      }
+    };
+    static_assert(STEADY || MODE == 0, "edge rows compute both halves");
+    if constexpr (MODE == 3) {
+      if (beta >= T(0) && __all(nu >= T(0))) {
+        ay_cells(std::integral_constant<int, 1>());
+      } else {
+        const T nu_prev = fma_t(-beta, (T)(t - 1 - H), ay);
+        if (beta >= T(0) && __all(nu_prev <= T(0)))
+          ay_cells(std::integral_constant<int, 2>());
+        else
+          ay_cells(std::integral_constant<int, 0>());
+      }
+    } else {
+      ay_cells(std::integral_constant<int, MODE>());
     }
 
     if (STEADY || t >= 2) {
@@ -180,16 +220,10 @@ struct Step2D {
 #pragma unroll
       for (int i = 0; i < W; ++i) {
         const T b = fma_t(D, dxf[i] - dxf[i + 1], a[i]);
-        const T del = dv ? in.a3[i] - b : T(0);
-        if (STEADY || r >= 1) emit(i, fma_t(D, in.del3[i] - del, in.a3[i]));
-        out.a3[i] = b;
-        out.del3[i] = del;
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < W; ++i) {
-        out.a3[i] = in.a3[i];
-        out.del3[i] = in.del3[i];
+        const T del = dv ? st.a3[i] - b : T(0);
+        if (STEADY || r >= 1) emit(i, fma_t(D, st.del3[i] - del, st.a3[i]));
+        st.a3[i] = b;
+        st.del3[i] = del;
       }
     }
   }
@@ -310,9 +344,15 @@ __device__ __forceinline__ void step2d_tile(
 
   auto load_row = [&](int t, int ys, T (&c)[W]) {
     const T* src = fbase + (size_t)t * rowpitch + (size_t)ys * nx;
+    // a fresh copy of the lane offset per row: the loads then take the
+    // scalar base + 32-bit offset form (the offset itself, held from
+    // before the row loop, would be widened to 64 bits once and every
+    // load would pay a 64-bit vector add)
+    uint32_t lo = koff[0];
+    if (INTERIOR) asm volatile("" : "+v"(lo));
 #pragma unroll
     for (int i = 0; i < W; ++i)
-      c[i] = INTERIOR ? row_load(src, (uint32_t)i * cell_stride, koff[0])
+      c[i] = INTERIOR ? row_load(src, (uint32_t)i * cell_stride, lo)
                       : row_load(src, 0u, koff[i]);
   };
 
@@ -347,6 +387,8 @@ __device__ __forceinline__ void step2d_tile(
     __builtin_amdgcn_s_setprio(3);
     const T* sb = stage + (t & 1) * O::SIZE + fj0 * O::STRIDE + fs;
     T* orow = frow0 + (size_t)(t - 3) * rowpitch;
+    uint32_t fl = flane;  // per row, as for the loads
+    asm volatile("" : "+v"(fl));
     constexpr int KL = O::K - 1;  // the last round covers planes < NV only
     T v[O::K];  // all LDS reads first, then the stores
 #pragma unroll
@@ -355,36 +397,38 @@ __device__ __forceinline__ void step2d_tile(
     v[KL] = last_in ? sb[KL * P * O::STRIDE] : T(0);
 #pragma unroll
     for (int k = 0; k < KL; ++k)
-      row_store<NT>(orow, (uint32_t)(k * P) * slot_bytes, flane, v[k]);
+      row_store<NT>(orow, (uint32_t)(k * P) * slot_bytes, fl, v[k]);
     __builtin_amdgcn_s_setprio(0);
-    row_store_if<NT>(orow, (uint32_t)(KL * P) * slot_bytes, flane, v[KL],
+    row_store_if<NT>(orow, (uint32_t)(KL * P) * slot_bytes, fl, v[KL],
                  last_in);
   };
-  auto run_row = [&](auto steady, int t, const T (&c)[W],
-                     const YState<T, W>& sin, YState<T, W>& sout) {
+  // kind: -1 for an edge row, else the steady row's skip mode
+  auto run_row = [&](auto kind, int t, const T (&c)[W], YState<T, W>& st) {
+    constexpr int KIND = decltype(kind)::value;
+    constexpr bool STEADY = KIND >= 0;
+    constexpr int MODE = STEADY ? KIND : 0;
     if (P == 1) {
       T* orow = orow0 + (size_t)(t - 3) * rowpitch;
-      K::template row<decltype(steady)::value>(
-          t, c, sin, sout, nxp, nxm, ay, beta, D, first, last, lane_l,
+      K::template row<STEADY, MODE>(
+          t, c, st, nxp, nxm, ay, beta, D, first, last, lane_l,
           lane_r, [&](int i, T v) {
             row_store<NT>(orow, (uint32_t)i * slot_bytes, store_lane, v);
           });
     } else {
       T* sb = sbase + (t & 1) * O::SIZE;
-      K::template row<decltype(steady)::value>(
-          t, c, sin, sout, nxp, nxm, ay, beta, D, first, last, lane_l,
+      K::template row<STEADY, MODE>(
+          t, c, st, nxp, nxm, ay, beta, D, first, last, lane_l,
           lane_r, [&](int i, T v) { sb[i * O::STRIDE] = v; });
-      if (decltype(steady)::value || t >= 3) flush(t);
+      if (STEADY || t >= 3) flush(t);
     }
   };
-  using steady_t = std::integral_constant<bool, true>;
-  using edge_t = std::integral_constant<bool, false>;
+  using edge_t = std::integral_constant<int, -1>;
 
-  YState<T, W> s0, s1;
+  YState<T, W> st;
 #pragma unroll
   for (int i = 0; i < W; ++i) {
-    s0.gp1[i] = s0.dpp1[i] = s0.gm1[i] = s0.em1[i] = s0.Fp1[i] =
-        s0.acc2[i] = s0.c1[i] = s0.a3[i] = s0.del3[i] = T(0);
+    st.gp1[i] = st.dpp1[i] = st.gm1[i] = st.em1[i] = st.Fp1[i] =
+        st.acc2[i] = st.c1[i] = st.a3[i] = st.del3[i] = T(0);
   }
 
   int ys = y + yoff0;  // row t = 0 comes from (y + shift*H) mod ny
@@ -397,46 +441,66 @@ __device__ __forceinline__ void step2d_tile(
   // rows 0..2 fill the streamed state; rows 3..NV-1 are the steady part
   // (NV - 3 rows, an even count, processed in pairs); rows NV..NV+2 drain
   // it.  Row t+1 is loaded before row t is processed.  The first and the
-  // last steady pair are peeled so that the loop body issues the same
+  // last steady pair are peeled so that the loop bodies issue the same
   // loads and stores on every trip and on entry: the memory counter waits
   // then only ever wait for the row about to be used, never for the
-  // stores issued after it.
+  // stores issued after it.  The pairs between them run in three loops,
+  // one per skip mode of the vy drift (the drift falls along the rows:
+  // first g- is zero on every lane, then neither half, then g+), so that
+  // each loop keeps its state in the same registers from trip to trip.
   T bufA[W], bufB[W];
   load_row(0, ys, bufA);
   ys = next_ys(ys);
   load_row(1, ys, bufB);
   ys = next_ys(ys);
-  run_row(edge_t(), 0, bufA, s0, s1);
+  run_row(edge_t(), 0, bufA, st);
   load_row(2, ys, bufA);
   ys = next_ys(ys);
-  run_row(edge_t(), 1, bufB, s1, s0);
+  run_row(edge_t(), 1, bufB, st);
   if (NV > 3) {
     load_row(3, ys, bufB);
     ys = next_ys(ys);
   }
-  run_row(edge_t(), 2, bufA, s0, s1);
-  // steady pair (t, t+1): row t is in bufB, state in s1
-  auto pair = [&](int t, bool load2) {
+  run_row(edge_t(), 2, bufA, st);
+  // steady pair (t, t+1): row t is in bufB
+  auto pair = [&](auto mode, int t, bool load2) {
     load_row(t + 1, ys, bufA);
     ys = next_ys(ys);
-    run_row(steady_t(), t, bufB, s1, s0);
+    run_row(mode, t, bufB, st);
     if (load2) {
       load_row(t + 2, ys, bufB);
       ys = next_ys(ys);
     }
-    run_row(steady_t(), t + 1, bufA, s0, s1);
+    run_row(mode, t + 1, bufA, st);
+  };
+  using pick_t = std::integral_constant<int, 3>;
+  // g- of rows t and t+1 is zero on every lane (the drift is >= 0 through
+  // row t+1); g+ of faces t and t+1 is zero (the drift is <= 0 from row t-1)
+  auto skip_gm = [&](int t) {
+    return beta >= T(0) && __all(fma_t(-beta, (T)(t + 1 - H), ay) >= T(0));
+  };
+  auto skip_gp = [&](int t) {
+    return beta >= T(0) && __all(fma_t(-beta, (T)(t - 1 - H), ay) <= T(0));
   };
   if (NV >= 7) {
-    pair(3, true);
+    pair(std::integral_constant<int, 0>(), 3, true);
+    int t = 5;
 #pragma unroll 1
-    for (int t = 5; t <= NV - 4; t += 2) pair(t, true);
-    pair(NV - 2, false);
+    for (; t <= NV - 4 && skip_gm(t); t += 2)
+      pair(std::integral_constant<int, 1>(), t, true);
+#pragma unroll 1
+    for (; t <= NV - 4 && !skip_gp(t); t += 2)
+      pair(std::integral_constant<int, 0>(), t, true);
+#pragma unroll 1
+    for (; t <= NV - 4; t += 2)
+      pair(std::integral_constant<int, 2>(), t, true);
+    pair(std::integral_constant<int, 0>(), NV - 2, false);
   } else if (NV == 5) {
-    pair(3, false);
+    pair(pick_t(), 3, false);
   }
-  run_row(edge_t(), NV, bufB, s1, s0);
-  run_row(edge_t(), NV + 1, bufB, s0, s1);
-  run_row(edge_t(), NV + 2, bufB, s1, s0);
+  run_row(edge_t(), NV, bufB, st);
+  run_row(edge_t(), NV + 1, bufB, st);
+  run_row(edge_t(), NV + 2, bufB, st);
 }
 
 // One workgroup = WGW wavefronts = G consecutive sites of spatial row y.  All
