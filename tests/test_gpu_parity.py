@@ -123,6 +123,73 @@ def test_2d_f32_parity_nv65():
     assert err <= FP32_REL_L2
 
 
+def _vy_drift_case(nv, flow, nx, ny, seed, dtype):
+    """A state with a chosen vertical flow u_y, which sets where the vy drift
+    nu(t) = (dt/tau_p)(u_y/dv - (t - h)) changes sign along the rows t: the
+    2D pass skips the split half of that drift that is zero on a whole
+    wavefront, in loops chosen by that sign change."""
+    from paper_1508_02899_amd import inputs
+    rng = np.random.default_rng(seed)
+    npdt = np.float64 if dtype == "f64" else np.float32
+    f0 = inputs.random_state(rng, (nv * nv, ny, nx), npdt)
+    L, dt = 2 * math.pi, 0.05
+    dx = L / nx
+    h = (nv - 1) // 2
+    dv = dx / dt
+    vmax = h * dv
+    ux = 0.5 * np.tanh(rng.standard_normal((ny, nx)))
+    uy = {
+        # sign change at a row a little past the middle / before it, the
+        # same for every site
+        "up": np.full((ny, nx), 0.3 * vmax),
+        "down": np.full((ny, nx), -0.3 * vmax),
+        # a different row for each wavefront of a workgroup
+        "wave": 0.5 * vmax * np.sin(2 * math.pi * np.arange(nx) / nx)
+        * np.ones((ny, 1)),
+        # past either end of the velocity axis: one half is zero throughout
+        "beyond": np.full((ny, nx), 1.2 * vmax),
+        "below": np.full((ny, nx), -1.2 * vmax),
+        # no drag at all (tau_p infinite): both halves are zero
+        "nodrag": np.zeros((ny, nx)),
+    }[flow]
+    u = np.stack([ux, uy])[None].astype(npdt)
+    umax = float(np.abs(u).max())
+    tau_p = math.inf if flow == "nodrag" else (dt / dv) * (umax + vmax) / 0.4
+    kappa = 0.2 * 0.5 * dv * dv / dt
+    p = dict(dim=2, dx=dx, dt=dt, tau_p=tau_p, kappa=kappa, s=1, nsub=1,
+             scheme="koren")
+    return f0, u, p
+
+
+@pytest.mark.parametrize("flow", ["up", "down", "wave", "beyond", "below",
+                                  "nodrag"])
+@pytest.mark.parametrize("nv", [17, 33, 65])
+def test_2d_vy_drift_half_skipped_where_zero(nv, flow):
+    """Each skip mode of the streamed vy drift, and the moves between them
+    at the same or at different rows across the wavefronts of a workgroup,
+    against the oracle (which always computes both split halves); 300
+    sites per row: several workgroups, interior and edge tiles, a ragged
+    tail."""
+    ny = 3 if nv == 65 else 4
+    say(f"2d vy-drift skip nv={nv} flow={flow}")
+    f0, u, p = _vy_drift_case(nv, flow, 300, ny, 700 + nv, "f32")
+    got = run_gpu(f0, u, p, 3)
+    want = run_oracle(f0, u, p, 3)
+    err = rel_l2(got, want)
+    say("  rel L2", err)
+    assert err <= FP32_REL_L2
+    assert np.isfinite(got).all()
+
+
+@pytest.mark.parametrize("flow", ["up", "wave", "below"])
+def test_2d_vy_drift_half_skipped_f64(flow):
+    say(f"2d f64 vy-drift skip nv=33 flow={flow}")
+    f0, u, p = _vy_drift_case(33, flow, 200, 3, 800, "f64")
+    got = run_gpu(f0, u, p, 3, dtype="f64")
+    want = run_oracle(f0, u, p, 3)
+    assert rel_l2(got, want) <= FP64_REL_L2
+
+
 @pytest.mark.parametrize("nx,ny,nv", [(1, 1, 9), (1, 5, 33), (7, 1, 17),
                                       (3, 2, 33), (2, 3, 65), (1, 2, 5)])
 def test_2d_degenerate_lattices(nx, ny, nv):
