@@ -54,21 +54,6 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
   return xcd * q + (xcd < r ? xcd : r) + k;
 }
 
-// The 2D pass: XCD x receives its blocks in rounds of g (the tiles of one
-// spatial row), and round r of XCD x is logical row 8 r + x, so that each
-// spatial row's tiles (which share the cache lines at their edges) run in
-// one L2 while the workgroups running at any moment cover one band of
-// consecutive rows, i.e. one stretch of memory per velocity plane instead
-// of one per XCD.  Blocks past the last full round of the 8 XCDs take the
-// contiguous ranges of xcd_remap.  A bijection of [0, n) for every g >= 1.
-__device__ __forceinline__ int xcd_rows(int b, int n, int g) {
-  const int full = n / (8 * g) * (8 * g);
-  if (b >= full) return full + xcd_remap(b - full, n - full);
-  const int xcd = b & 7, k = b >> 3;
-  const int r = k / g;
-  return (r * 8 + xcd) * g + (k - r * g);
-}
-
 // Lane-to-lane exchange inside a wavefront (ds_bpermute; no LDS storage).
 __device__ __forceinline__ float lane_read(float v, int src) {
   return __int_as_float(
