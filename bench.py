@@ -362,9 +362,13 @@ def bench_coarse(args, w):
     if not 0 <= eps_min < 1:
         sys.exit("--line-eps must be in [0, 1)")
     T_val, T_eval = 200, 200
+    # the held-out flow continues past the evaluation for the timing; its
+    # scale is the r.m.s. of its first 410 slices whatever K and W are, so
+    # the evaluated slices do not depend on the timing parameters
     flows = CC.workload_flows(n, nvf, w["vmax"],
                               {"train": 400, "valid": T_val + 25,
-                               "eval": T_eval + W + K})
+                               "eval": T_eval + W + K},
+                              norm={"eval": 410})
     thresholds = tuple(e for e in (8e-3, 1.2e-2, 1.8e-2, 2.4e-2, 3.2e-2,
                                    4.8e-2, 6.4e-2) if e >= eps_min)
     if not thresholds:

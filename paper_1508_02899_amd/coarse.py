@@ -487,13 +487,15 @@ def select_on_validation(fine_spec: LatticeSpec, coarse_spec: LatticeSpec,
 
 
 def workload_flows(n: int, nv_fine: int, vmax: float, lengths: dict,
-                   seeds: dict | None = None):
+                   seeds: dict | None = None, norm: dict | None = None):
     """The three distinct synthetic flows of the coarse-model workflow on an
     n^2 periodic lattice (the 32-mode streamfunction flow with tau_f = 1,
     sampled every step dt of the fine lattice, nv_fine velocities up to
     Vmax = vmax u_rms): ``lengths`` maps "train", "valid", "eval" to their
-    slice counts.  Each is a callable k -> slice [1, 2, n, n] (device) with
-    the slices stacked in .all."""
+    slice counts; ``norm`` may map a flow to the number of leading slices
+    whose r.m.s. sets its scale (at least that many are generated), so that
+    its first slices do not depend on how many follow.  Each is a callable
+    k -> slice [1, 2, n, n] (device) with the slices stacked in .all."""
     torch = _torch()
     from . import inputs
     if seeds is None:
@@ -502,9 +504,12 @@ def workload_flows(n: int, nv_fine: int, vmax: float, lengths: dict,
     L = 2 * math.pi
     dt = (L / n) / (vmax / ((nv_fine - 1) // 2))
     out = {}
+    norm = norm or {}
     for k, nsl in lengths.items():
+        m = norm.get(k)
         u = torch.from_numpy(inputs.flow2d_streamfunction(
-            n, L, nsl, kmax=32, tau_f=1.0, dt=dt, seed=seeds[k])).cuda()
+            n, L, max(nsl, m or 0), kmax=32, tau_f=1.0, dt=dt, seed=seeds[k],
+            norm_slices=m)).cuda()
         fn = (lambda uu: (lambda j: uu[j:j + 1]))(u)
         fn.all = u
         out[k] = fn

@@ -203,11 +203,15 @@ def flow2d_modes(n: int, L: float, nslices: int, *, kmin: int = 1,
 def flow2d_streamfunction(n: int, L: float, nslices: int, *, kmin: int = 1,
                           kmax: int = 32, slope: float = -3.0,
                           urms: float = 1.0, tau_f: float = 1.0,
-                          dt: float = 1.0, seed: int = 0, dtype=np.float32):
+                          dt: float = 1.0, seed: int = 0, dtype=np.float32,
+                          norm_slices: int | None = None):
     """u[slice, 2, n, n] = (d_y psi, -d_x psi) for a random streamfunction
     with energy shell spectrum E(k) ~ k^slope on kmin <= |k| <= kmax and OU
     time evolution (correlation time tau_f) of every Fourier mode
-    (prestaged form of flow2d_modes, evaluated with inverse real FFTs)."""
+    (prestaged form of flow2d_modes, evaluated with inverse real FFTs).
+    The r.m.s. that sets the scale is taken over the first norm_slices
+    slices (all of them by default), so that a longer flow with a fixed
+    norm_slices starts with the same slices as a shorter one."""
     k2pi = 2.0 * np.pi / L
     out = np.empty((nslices, 2, n, n), dtype=np.float64)
     for s, (KX, KY, psi_hat) in enumerate(_psi_hat_slices(
@@ -215,8 +219,11 @@ def flow2d_streamfunction(n: int, L: float, nslices: int, *, kmin: int = 1,
         out[s, 0] = np.fft.irfft2(1j * KY * k2pi * psi_hat, s=(n, n))
         out[s, 1] = np.fft.irfft2(-1j * KX * k2pi * psi_hat, s=(n, n))
     # ensemble normalisation: the stationary per-component variance is the
-    # same for every slice; scale by the r.m.s. over all slices
-    r = np.sqrt(0.5 * (np.mean(out[:, 0] ** 2) + np.mean(out[:, 1] ** 2)))
+    # same for every slice; scale by the r.m.s. over the leading slices
+    m = nslices if norm_slices is None else norm_slices
+    if not 1 <= m <= nslices:
+        raise ValueError("norm_slices must be in 1..nslices")
+    r = np.sqrt(0.5 * (np.mean(out[:m, 0] ** 2) + np.mean(out[:m, 1] ** 2)))
     out *= urms / r
     return np.ascontiguousarray(out.astype(dtype))
 

@@ -56,6 +56,26 @@ def test_flow2d_divergence_free_and_spectrum():
     assert slope == pytest.approx(-3.0, abs=0.4)
 
 
+def test_flow2d_fixed_normalisation_keeps_the_leading_slices():
+    """With the scale taken over a fixed number of leading slices, a longer
+    flow starts with the slices of a shorter one (the OU draws are
+    sequential); by default the scale covers every slice, so the two
+    differ."""
+    kw = dict(kmax=8, seed=11, dtype=np.float64)
+    short = inputs.flow2d_streamfunction(32, 2 * math.pi, 10, **kw)
+    longer = inputs.flow2d_streamfunction(32, 2 * math.pi, 25, norm_slices=10,
+                                          **kw)
+    assert np.array_equal(short, longer[:10])
+    u = longer[:10]
+    assert np.sqrt(np.mean(u ** 2)) == pytest.approx(1.0, rel=1e-12)
+    whole = inputs.flow2d_streamfunction(32, 2 * math.pi, 25, **kw)
+    assert not np.array_equal(short, whole[:10])
+    for bad in (0, 26):
+        with pytest.raises(ValueError):
+            inputs.flow2d_streamfunction(32, 2 * math.pi, 25, norm_slices=bad,
+                                         **kw)
+
+
 def test_cellular_flow_divergence_free():
     n, L = 64, 2 * math.pi
     u = inputs.cellular_flow(n, L, dtype=np.float64)[0]
