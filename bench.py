@@ -363,12 +363,12 @@ def bench_coarse(args, w):
         sys.exit("--line-eps must be in [0, 1)")
     T_val, T_eval = 200, 200
     # the held-out flow continues past the evaluation for the timing; its
-    # scale is the r.m.s. of its first 410 slices whatever K and W are, so
-    # the evaluated slices do not depend on the timing parameters
+    # scale is the r.m.s. of the evaluated slices (u_rms = 1 over them)
+    # whatever K and W are, so they do not depend on the timing parameters
     flows = CC.workload_flows(n, nvf, w["vmax"],
                               {"train": 400, "valid": T_val + 25,
                                "eval": T_eval + W + K},
-                              norm={"eval": 410})
+                              norm={"eval": T_eval})
     thresholds = tuple(e for e in (8e-3, 1.2e-2, 1.8e-2, 2.4e-2, 3.2e-2,
                                    4.8e-2, 6.4e-2) if e >= eps_min)
     if not thresholds:
