@@ -10,7 +10,7 @@ third.  Target: at least 4x the fine lattice's throughput with the
 velocity-variance and distance-averaged <rho_r^2> errors (Sec. 4.2.1)
 within 2 % of the restricted fine state, asserted for the Stokes numbers
 that meet it (0.5 and 5); St = 2 does not (its variance error stays near
-3.5 %) and is not asserted.  St = 5 meets it with a short a-posteriori
+3 %) and is not asserted.  St = 5 meets it with a short a-posteriori
 stage (one run, 10 iterations: 20 s); St = 0.5 only with the full one
 (two runs, up to 80 iterations: about four minutes, over the time a GPU
 test may run without output), so that case carries the gpu_long marker
