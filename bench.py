@@ -140,12 +140,13 @@ def baseline_threads() -> int:
     return len(os.sched_getaffinity(0))
 
 
-def cpu_baseline(w, name, dx, dv, dt, tau_p):
-    """The FP64 oracle on a bounded sample of the workload: its plain
-    single-threaded build in this process, then the same source built with
-    OpenMP over sites, in a process of its own with OMP_NUM_THREADS set."""
+def cpu_baseline(spec):
+    """The FP64 oracle on a bounded sample of the workload (``spec``, see
+    cpu_sample): its plain single-threaded build in this process, then the
+    same source built with OpenMP over sites, in a process of its own with
+    OMP_NUM_THREADS set."""
     import subprocess
-    one = cpu_sample(w, dx, dv, dt, tau_p)
+    one = cpu_sample(spec)
     n = baseline_threads()
     out = {"value": one["value"], "unit": "GCUPS", "cores": 1,
            "kind": "oracle", "sample": one["sample"],
@@ -157,7 +158,7 @@ def cpu_baseline(w, name, dx, dv, dt, tau_p):
         env = dict(os.environ, ORACLE_LIB=oracle.OMP_SO,
                    OMP_NUM_THREADS=str(n))
         args = [sys.executable, os.path.abspath(__file__), "--cpu-sample",
-                json.dumps(dict(w=w, dx=dx, dv=dv, dt=dt, tau_p=tau_p))]
+                json.dumps(spec)]
         r = subprocess.run(args, env=env, capture_output=True, text=True,
                            timeout=600)
         if r.returncode == 0:
@@ -169,9 +170,41 @@ def cpu_baseline(w, name, dx, dv, dt, tau_p):
     return out
 
 
-def cpu_sample(w, dx, dv, dt, tau_p):
+def cpu_sample(spec):
     """Time the oracle (whichever build ORACLE_LIB selects) on the bounded
-    sample of the workload."""
+    sample of a workload: spec["kind"] "lattice" (w, dx, dv, dt, tau_p of
+    one lattice) or "batch" (w and the step count for every member)."""
+    scheme = spec.get("scheme", "koren")
+    if spec["kind"] == "batch":
+        return cpu_sample_batch(spec["w"], spec["steps"], scheme)
+    return cpu_sample_lattice(spec["w"], spec["dx"], spec["dv"], spec["dt"],
+                              spec["tau_p"], scheme)
+
+
+def cpu_sample_batch(w, steps, scheme):
+    """Every member of the batched workload for ``steps`` steps, one after
+    another, with its own flow (renewed every 50 steps)."""
+    import numpy as np
+
+    import oracle
+    mems, states, flows = batch_members(w["batch"], steps)
+    cells = 0
+    t0 = time.perf_counter()
+    for m, f0, u in zip(mems, states, flows):
+        oracle.step(f0.astype(np.float64), u[:, None, :].astype(np.float64),
+                    dim=1, dx=m.dx, tau_p=m.tau_p, kappa=m.kappa, dt=m.dt,
+                    nsteps=steps, u_hold=m.u_hold, scheme=scheme)
+        cells += m.nx * m.nv
+    el = time.perf_counter() - t0
+    return {"value": cells * steps / el / 1e9,
+            "sample": f"all {len(mems)} members of the batch, {steps} steps "
+                      "each, same parameters",
+            "seconds": round(el, 3)}
+
+
+def cpu_sample_lattice(w, dx, dv, dt, tau_p, scheme):
+    """The lattice workloads' sample: a crop of a 2D lattice, or a whole 1D
+    lattice for a bounded number of steps."""
     import numpy as np
 
     import oracle
@@ -197,7 +230,7 @@ def cpu_sample(w, dx, dv, dt, tau_p):
     t0 = time.perf_counter()
     oracle.step(f0.astype(np.float64), u.astype(np.float64), dim=w["dim"],
                 dx=dx, tau_p=tau_p, kappa=w["kappa"], dt=dt, nsteps=steps,
-                s=w["s"])
+                s=w["s"], scheme=scheme)
     el = time.perf_counter() - t0
     return {"value": cells * steps / el / 1e9, "sample": sample,
             "seconds": round(el, 3)}
@@ -344,6 +377,10 @@ def bench_batch(args, w):
                                 "k_batch1d (all classes)")},
     }
     b.close()
+    if not args.no_cpu_baseline and not w.get("st_set"):
+        log("bench: timing the oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(dict(kind="batch", w=w, steps=4,
+                                                scheme=args.scheme))
     print(json.dumps(out), flush=True)
 
 
@@ -722,8 +759,7 @@ def main():
     args = ap.parse_args()
     if args.cpu_sample:  # the threaded oracle leg of the CPU baseline
         p = json.loads(args.cpu_sample)
-        print(json.dumps(cpu_sample(p["w"], p["dx"], p["dv"], p["dt"],
-                                    p["tau_p"])))
+        print(json.dumps(cpu_sample(p)))
         return 0
     if args.summarize:
         return summarize(args)
@@ -928,7 +964,9 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on a bounded sample")
-        out["cpu_baseline"] = cpu_baseline(w, args.workload, dx, dv, dt, tau_p)
+        out["cpu_baseline"] = cpu_baseline(dict(kind="lattice", w=w, dx=dx,
+                                                dv=dv, dt=dt, tau_p=tau_p,
+                                                scheme=args.scheme))
     print(json.dumps(out), flush=True)
 
 
