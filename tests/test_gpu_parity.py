@@ -232,6 +232,49 @@ def test_nsub_stride_and_u_hold(dim):
     assert err <= FP32_REL_L2
 
 
+@pytest.mark.parametrize("dim", [1, 2])
+def test_drift_without_diffusion(dim):
+    """kappa = 0 is accepted and gives the oracle's drift-only update."""
+    nx, ny = (300, 1) if dim == 1 else (70, 5)
+    say(f"{dim}d drift only (kappa = 0)")
+    f0, u, p = make_case(dim, nx, 17, ny=ny, seed=920 + dim)
+    p = dict(p, kappa=0.0)
+    got = run_gpu(f0, u, p, 4)
+    want = run_oracle(f0, u, p, 4)
+    err = rel_l2(got, want)
+    say("  rel L2", err)
+    assert err <= FP32_REL_L2
+
+
+def test_work_runs_on_the_given_stream():
+    """The library queues its work on the stream it is given: a side stream
+    is held up by a bounded GPU sleep, then the state is refilled and
+    stepped on it with no host synchronisation in between; work queued
+    anywhere else would read the zeros left before the refill."""
+    import torch
+    from paper_1508_02899_amd import Lattice
+    from helpers import spec_for
+    say("2d step queued behind a sleeping side stream")
+    f0, u, p = make_case(2, 70, 9, ny=6, seed=930)
+    want = run_oracle(f0, u, p, 3)
+    side = torch.cuda.Stream()  # default priority
+    lat = Lattice(spec_for(f0, p, "f32"), stream=side)
+    src = torch.from_numpy(np.ascontiguousarray(f0)).cuda()
+    ut = torch.from_numpy(np.ascontiguousarray(u)).cuda()
+    f = torch.zeros_like(src)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        torch.cuda._sleep(50_000_000)  # about 20 ms of spinning
+        f.copy_(src)
+    lat.step(f, ut, p["tau_p"], p["kappa"], p["dt"], 3)
+    lat.sync()
+    torch.cuda.synchronize()
+    err = rel_l2(f.cpu().numpy(), want)
+    lat.close()
+    say("  rel L2", err)
+    assert err <= FP32_REL_L2
+
+
 @pytest.mark.parametrize("dim,nv", [(1, 33), (1, 129), (2, 9), (2, 33)])
 def test_pure_streaming_bit_exact(dim, nv):
     """tau_p = inf and kappa = 0: exact periodic permutation (np.roll)."""
