@@ -178,7 +178,7 @@ def cpu_sample(spec):
     if spec["kind"] == "batch":
         return cpu_sample_batch(spec["w"], spec["steps"], scheme)
     return cpu_sample_lattice(spec["w"], spec["dx"], spec["dv"], spec["dt"],
-                              spec["tau_p"], scheme)
+                              spec["tau_p"], scheme, spec.get("nsub", 1))
 
 
 def cpu_sample_batch(w, steps, scheme):
@@ -202,21 +202,26 @@ def cpu_sample_batch(w, steps, scheme):
             "seconds": round(el, 3)}
 
 
-def cpu_sample_lattice(w, dx, dv, dt, tau_p, scheme):
+def cpu_sample_lattice(w, dx, dv, dt, tau_p, scheme, nsub=1):
     """The lattice workloads' sample: a crop of a 2D lattice, or a whole 1D
-    lattice for a bounded number of steps."""
+    lattice for a bounded number of steps (nsub collision sub-steps per
+    step)."""
     import numpy as np
 
     import oracle
     from paper_1508_02899_amd import inputs
     L = 2 * math.pi
     if w["dim"] == 2:
-        m = min(w["n"], 256 if w["nv"] <= 33 else 128)
-        steps = 4
+        # about 10-30 s of single-threaded oracle time
+        m = min(w["n"], 256 if w["nv"] <= 33 else (128 if nsub == 1 else 64))
+        steps = max(1, 4 // nsub)
         u = make_flow(w, 1, dt, np.float32)[:, :, :m, :m]
         f0 = inputs.gaussian_ic(2, m, w["nv"], dx, dv, ny=m)
         sample = (f"{m}x{m} sites (a crop of the {w['n']}x{w['n']} lattice) "
-                  f"x {w['nv']}^2 velocities, {steps} steps, same parameters")
+                  f"x {w['nv']}^2 velocities, {steps} step"
+                  + ("s" if steps != 1 else "")
+                  + (f" of {nsub} collision sub-steps" if nsub > 1 else "")
+                  + ", same parameters")
         cells = m * m * w["nv"] ** 2
     else:
         m = w["n"]
@@ -230,7 +235,7 @@ def cpu_sample_lattice(w, dx, dv, dt, tau_p, scheme):
     t0 = time.perf_counter()
     oracle.step(f0.astype(np.float64), u.astype(np.float64), dim=w["dim"],
                 dx=dx, tau_p=tau_p, kappa=w["kappa"], dt=dt, nsteps=steps,
-                s=w["s"], scheme=scheme)
+                s=w["s"], scheme=scheme, nsub=nsub)
     el = time.perf_counter() - t0
     return {"value": cells * steps / el / 1e9, "sample": sample,
             "seconds": round(el, 3)}
@@ -481,6 +486,16 @@ def bench_coarse(args, w):
                      "flops_per_launch": flops,
                      "avg_launch_us": round(t_corr * 1e6, 2)},
     }
+    if not args.no_cpu_baseline:
+        # the oracle's fine lattice at the Stokes number of `value` (the
+        # rate the coarse model stands in for)
+        log("bench: timing the oracle on a bounded sample")
+        L = 2 * math.pi
+        dv = w["vmax"] / ((nvf - 1) // 2)
+        dx = L / n
+        out["cpu_baseline"] = cpu_baseline(dict(
+            kind="lattice", w=w, dx=dx, dv=dv, dt=dx / dv, tau_p=head * L,
+            scheme="koren", nsub=int(per[head]["nsub_fine"])))
     print(json.dumps(out), flush=True)
 
 
