@@ -125,8 +125,14 @@ __global__ __launch_bounds__(parts_threads<NV>()) void k_batch1d_parts(
 // units); every tile of a member, at every step, is updated by a
 // workgroup of the member's XCD.  Each XCD has a work counter over its
 // (step, tile) items, numbered step-major with the tiles of one step
-// listed member by member; its workgroups take chunks of consecutive items
-// from it.  A member's tile of step t > 0 starts once the member's counter
+// listed member by member; its workgroups take chunks from it.  The
+// chunks come in blocks of `stride` (1 or 2): a block covers stride x
+// chunk consecutive items, and its chunk r holds items r, r + stride,
+// r + 2 stride, ... of them, so that the workgroups sharing a block work on
+// neighbouring tiles at the same time (fewer places in memory at once;
+// 5 % shorter steps on configuration 4 with stride 2, longer with 4 or
+// more, where a member's step is spread over too many workgroups that then
+// wait for each other).  A member's tile of step t > 0 starts once the member's counter
 // of finished tiles shows all of its step t-1 tiles done: the pull
 // streaming of step t reads any of them, and they have finished reading the
 // buffer that step t writes.  Because producer and consumer share one L2,
@@ -135,8 +141,15 @@ __global__ __launch_bounds__(parts_threads<NV>()) void k_batch1d_parts(
 // another XCD's L2 would need on every tile: measured 15x slower), and
 // consumed after invalidating the compute unit's L1.
 // Deadlock freedom: a workgroup publishes its finished items before it
-// ever waits, and only waits on items taken before its own, each held by a
-// running workgroup, so the earliest unfinished item never waits.  Every
+// ever waits, works its chunk's items in increasing order, and only waits
+// on smaller items (of the previous step).  Take the smallest unfinished
+// item u: if its chunk is held, the holder is at u and u's items are all
+// finished, so it proceeds.  If not, every chunk of an earlier block is
+// finished (its items are all below u), so a workgroup holding one of them
+// moves on to the next chunk; only the other chunks of u's block (at most
+// stride - 1) can be held by waiting workgroups, so with at least stride
+// workgroups running on the XCD one of them takes u's chunk.  (A launch
+// that runs fewer ends at the bounded waits with ETIMEOUT.)  Every
 // class uses eight wavefronts per workgroup so that one kernel serves all
 // of them (split-column tiles of parts1d.h).
 template <int NV>
@@ -162,7 +175,7 @@ __device__ __forceinline__ void resident_run(float* tile,
                                              float* __restrict__ fout,
                                              const float* __restrict__ u,
                                              const BatchMember& m, int x0,
-                                             int n, int slice) {
+                                             int n, int slice, int stride) {
   constexpr int P = ResidentShape<NV>::P;
   using PT = ResTile<NV>;
   int jump = 0;  // (P s) mod nx, no division
@@ -175,8 +188,9 @@ __device__ __forceinline__ void resident_run(float* tile,
   const float* const us = u + m.u_off + (int64_t)slice * m.nx;
   float r[PT::K];
   PT::load(src, m.nx, m.pitch, x0, m.step_mod, m.init_off, jump, r);
+  const int hop = stride * PT::G;
   for (int q = 0; q < n; ++q) {
-    const int xq = x0 + q * PT::G;
+    const int xq = x0 + q * hop;
     PT::put(tile, r);
     // the flow value first: the memory counter is in order, and the
     // collision must not wait for the next tile's loads
@@ -184,7 +198,7 @@ __device__ __forceinline__ void resident_run(float* tile,
     __syncthreads();
     // unconditional, so that the counter waits stay exact (past the last
     // tile: idle loads of one element)
-    PT::load(src, m.nx, m.pitch, q + 1 < n ? xq + PT::G : xq, m.step_mod,
+    PT::load(src, m.nx, m.pitch, q + 1 < n ? xq + hop : xq, m.step_mod,
              m.init_off, jump, r, q + 1 >= n);
     PT::template collide<KOREN>(tile, alpha, m.nsub, m.beta, m.D);
     __syncthreads();
@@ -197,12 +211,12 @@ template <bool KOREN>
 __device__ __forceinline__ void resident_dispatch(
     float* tile, const float* __restrict__ fin, float* __restrict__ fout,
     const float* __restrict__ u, const BatchMember& m, int x0, int n,
-    int slice) {
+    int slice, int stride) {
   switch (m.nv) {
-    case 17: resident_run<17, KOREN>(tile, fin, fout, u, m, x0, n, slice); break;
-    case 33: resident_run<33, KOREN>(tile, fin, fout, u, m, x0, n, slice); break;
-    case 65: resident_run<65, KOREN>(tile, fin, fout, u, m, x0, n, slice); break;
-    default: resident_run<129, KOREN>(tile, fin, fout, u, m, x0, n, slice); break;
+    case 17: resident_run<17, KOREN>(tile, fin, fout, u, m, x0, n, slice, stride); break;
+    case 33: resident_run<33, KOREN>(tile, fin, fout, u, m, x0, n, slice, stride); break;
+    case 65: resident_run<65, KOREN>(tile, fin, fout, u, m, x0, n, slice, stride); break;
+    default: resident_run<129, KOREN>(tile, fin, fout, u, m, x0, n, slice, stride); break;
   }
 }
 
@@ -248,7 +262,7 @@ __global__ __launch_bounds__(64 * kResW) void k_batch_resident(
     const BatchTile* __restrict__ tiles, const int* __restrict__ goff,
     int nxcd, const int* __restrict__ mtiles, const int* __restrict__ mflag,
     int step0, int nsteps, int chunk, int* __restrict__ sync,
-    int wait_limit) {
+    int wait_limit, int stride) {
   __shared__ float tile[kResLds];
   __shared__ int s_base[2];
   __shared__ int s_go;
@@ -279,22 +293,29 @@ __global__ __launch_bounds__(64 * kResW) void k_batch_resident(
     pend = 0;
   };
   while (!stop) {
-    const int base = s_base[slot];
-    if (base >= total) break;
+    const int cidx = s_base[slot] / chunk;
+    const int blk = cidx / stride;
+    const int first = blk * stride * chunk + (cidx - blk * stride);
+    if (first >= total) break;
     // the next chunk's number travels while this one is worked on
     if (tid == 0)
       s_base[slot ^ 1] = __hip_atomic_fetch_add(queue, chunk,
                                                 __ATOMIC_RELAXED,
                                                 __HIP_MEMORY_SCOPE_AGENT);
-    const int end = base + chunk < total ? base + chunk : total;
-    // the chunk as runs of consecutive tiles of one member at one step
-    for (int i = base; i < end;) {
+    // the chunk's items first, first + stride, ...: runs of tiles of one
+    // member at one step, stride tiles apart
+    for (int j = 0; j < chunk;) {
+      const int i = first + j * stride;
+      if (i >= total) break;
       const int t = i / T;
       const BatchTile tl = tiles[g0 + (i - t * T)];
       const BatchMember m = mem[tl.member];
-      const int left = mtiles[tl.member] - tl.x0 / resident_g(m.nv);
-      const int n = end - i < left ? end - i : left;
-      i += n;
+      const int k = tl.x0 / resident_g(m.nv);
+      int n = (mtiles[tl.member] - k + stride - 1) / stride;
+      if (n > chunk - j) n = chunk - j;
+      const int rest = (total - i + stride - 1) / stride;
+      if (n > rest) n = rest;
+      j += n;
       if (mflag[tl.member] != 0) continue;  // frozen members do nothing
       if (tl.member != cur_m || t != cur_t) {
         flush();
@@ -329,7 +350,7 @@ __global__ __launch_bounds__(64 * kResW) void k_batch_resident(
       float* const fin = (t & 1) ? b1 : b0;
       float* const fout = (t & 1) ? b0 : b1;
       const int sl = m.u_hold > 0 ? (step0 + t) / m.u_hold : 0;
-      resident_dispatch<KOREN>(tile, fin, fout, u, m, tl.x0, n, sl);
+      resident_dispatch<KOREN>(tile, fin, fout, u, m, tl.x0, n, sl, stride);
       pend += n;
     }
     __syncthreads();  // s_base[slot ^ 1] is written
@@ -509,7 +530,7 @@ hipError_t launch_batch_resident(const ResidentLaunch& a, hipStream_t s) {
     hipLaunchKernelGGL(kernel, dim3(a.grid), dim3(64 * kResW), 0, s, a.b0,
                        a.b1, a.u, a.mem, a.tiles, a.goff, a.nxcd, a.mtiles,
                        a.mflag, a.step0, a.nsteps, a.chunk, a.sync,
-                       a.wait_limit);
+                       a.wait_limit, a.stride);
   };
   if (a.koren)
     go(k_batch_resident<true>);

@@ -572,6 +572,11 @@ int lattice_batch_step(lattice_batch_t* B, float* f, const float* u,
       a.step0 = (int)s0;
       a.nsteps = (int)n;
       a.chunk = B->r_chunk;
+      // pairs of workgroups share their chunks' items (item stride 2):
+      // 5 % shorter steps on configuration 4 than one chunk per
+      // workgroup; needs two co-resident workgroups per XCD, which the
+      // grid gives unless it holds fewer than two per XCD
+      a.stride = B->r_grid / B->r_nxcd >= 2 ? 2 : 1;
       a.sync = B->d_sync;
       a.wait_limit = B->wait_limit;
       BCHK(B, lat::launch_batch_resident(a, B->stream));

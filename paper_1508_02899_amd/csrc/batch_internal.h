@@ -78,6 +78,7 @@ struct ResidentLaunch {
   int step0;   // step index of local step 0 within the call (flow slices)
   int nsteps;  // (largest goff span) * nsteps + grid * chunk < 2^31
   int chunk;   // items per work-counter fetch
+  int stride;  // chunks of a block of `stride` interleave their items
   int* sync;
   int wait_limit;
 };

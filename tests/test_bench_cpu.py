@@ -58,4 +58,8 @@ def test_recorded_counters_match_the_kernel_sources():
         else:
             assert t["kernel_hash"] == bench.kernel_hash(w["dim"]), f
             assert bench.load_traffic(t["workload"]) == t["bytes_per_launch"]
-        assert 0.99 < t["traffic_over_algorithmic"] < 1.05, f
+        # the lattice passes re-read nothing; the batched kernel re-reads
+        # tile edges that two workgroups share (its paired chunks trade
+        # about 8 % more reads for shorter steps)
+        top = 1.10 if w.get("batch") else 1.05
+        assert 0.99 < t["traffic_over_algorithmic"] < top, f
