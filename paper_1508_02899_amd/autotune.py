@@ -154,7 +154,7 @@ def tune_batch(batch, flows, scheme: str = "koren", steps: int = 20,
 
 RESIDENT_CAPS = (17, 33, 65, 129)
 # (workgroups per CU (0: as many as fit), items per work-counter fetch)
-RESIDENT_CANDIDATES = ((0, 4), (0, 8), (0, 16), (0, 32), (2, 16))
+RESIDENT_CANDIDATES = ((0, 4), (0, 8), (0, 16), (0, 32), (0, 64), (2, 16))
 # the schedules are compared over this many steps, the per-step one
 # replaying a graph of as many (as a long run does)
 SCHEDULE_STEPS = 50
