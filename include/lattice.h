@@ -417,7 +417,9 @@ enum { LATTICE_BATCH_PER_STEP = 0, LATTICE_BATCH_RESIDENT = 1 };
  * every step, are updated on its XCD: workgroups take chunks of `chunk`
  * (step, tile) items from their XCD's device work counter, in step order
  * (the tiles of one step member by member; split-column tiles, 128 sites
- * for nv 17, 33, 65 and 64 for nv 129).  A member's tile of step t > 0
+ * for nv 17, 33, 65 and 64 for nv 129), two chunks at a time interleaved
+ * (one holds the even, the other the odd items of their 2 x chunk), so
+ * that two workgroups work on neighbouring tiles.  A member's tile of step t > 0
  * starts once the member's device counter of finished tiles shows all of
  * its step t-1 tiles done (they wrote what the pull streaming of step t
  * reads, and have read the buffer that step t writes): a barrier per
@@ -425,9 +427,12 @@ enum { LATTICE_BATCH_PER_STEP = 0, LATTICE_BATCH_RESIDENT = 1 };
  * velocity lattices overlap.  Finished tiles are published through the
  * shared L2 of the XCD (stores complete before the count; the reader's L1
  * dropped before loading).  A workgroup publishes its finished tiles
- * before it waits and only waits on items taken before its own, so the
- * queues drain whatever the residency; a launch that leaves items of some
- * XCD untaken (no workgroup ran there) is reported like a time-out.
+ * before it waits and only waits on smaller items, so the queues drain as
+ * long as two of the launch's workgroups run at once on each XCD (the
+ * grid always holds at least that many; a device shared with other work
+ * that leaves fewer ends in the bounded waits below); a launch that leaves
+ * items of some XCD untaken (no workgroup ran there) is reported like a
+ * time-out.
  * Every member's nv must be 17, 33, 65 or 129 (else ENOTSUP; the schedule
  * is unchanged); use_graph and graph_steps of lattice_batch_step are then
  * ignored, and the per-class decompositions of lattice_batch_tune are not
